@@ -1,0 +1,172 @@
+/*
+ * wmd.h -- C ABI of the gfx950 Sinkhorn Word Mover's Distance library.
+ *
+ * The library scores query documents against a resident corpus of target
+ * documents with the entropic (Sinkhorn) word mover's distance of
+ * arXiv 2107.06433, Algorithm 1:
+ *
+ *   select the query's nonzero words (r), M = Euclidean cost between the
+ *   query words and the vocabulary, K = exp(-lambda M), x = 1/v_r, then
+ *   max_iter times  x = diag(1/r) K (c .* 1/(K^T (1/x))),  and finally
+ *   u = 1/x, v = c .* 1/(K^T u), d_k = sum(u .* ((K .* M) v))_k.
+ *
+ * The sparse steps run as the fused SDDMM-SpMM of Section III-C: for every
+ * nonzero c_jk the dot product s = K_j . u_k and the update x_k += K_j c_jk / s
+ * happen together, so the sparse intermediate v is never stored.
+ *
+ * Conventions for every function below
+ *  - All device pointers refer to memory on the device that is current when
+ *    the call is made; the library never allocates device memory.  Device
+ *    buffers are supplied by the caller (typically torch tensors) and are
+ *    BORROWED: they must stay valid for as long as the library may use them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - Functions return a wmd_status and never throw.  On failure
+ *    wmd_last_error() returns a message for the calling thread.
+ *  - Distances are float32.  Arithmetic is float32 throughout the iteration;
+ *    only the cost-matrix GEMM may use bf16 inputs (WMD_CDIST_BF16).
+ */
+#ifndef WMD_H
+#define WMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WMD_OK = 0,
+  WMD_ERR_INVALID_ARGUMENT = 1,    /* bad pointer, size, id, weight or option      */
+  WMD_ERR_WORKSPACE_TOO_SMALL = 2, /* workspace_bytes below the *_workspace_bytes() */
+  WMD_ERR_DEVICE = 3,              /* a HIP call failed; message holds its string   */
+  WMD_ERR_NOT_SUPPORTED = 4        /* a shape beyond the library's limits           */
+} wmd_status;
+
+/* Precision of the cost-matrix GEMM  q_i . e_j  (Section III-B-1, cdist).
+ * FP32: float32 inputs and accumulation.  BF16: bf16-rounded inputs, float32
+ * accumulation; the norms |q|^2, |e|^2, the square root, exp and every
+ * Sinkhorn step stay float32 either way. */
+typedef enum { WMD_CDIST_FP32 = 0, WMD_CDIST_BF16 = 1 } wmd_cdist;
+
+/* How the max_iter fused SDDMM-SpMM passes are scheduled.
+ *  RESIDENT      one launch per (query, document-length bucket) runs every
+ *                iteration and the final pass; each document's rows of K^T
+ *                are gathered once and kept in registers.
+ *  PER_ITERATION one launch per iteration (u round-trips through device
+ *                memory, rows of K^T re-gathered each pass), as Section III-C
+ *                runs one SDDMM_SpMM call per loop trip, then a final launch.
+ *  UNFUSED       SDDMM and SpMM as two launches per iteration with the sparse
+ *                intermediate w stored in device memory (the unfused baseline
+ *                of the fusion experiment, Section V).
+ *  AUTO          RESIDENT. */
+typedef enum {
+  WMD_SCHEDULE_AUTO = 0,
+  WMD_SCHEDULE_RESIDENT = 1,
+  WMD_SCHEDULE_PER_ITERATION = 2,
+  WMD_SCHEDULE_UNFUSED = 3
+} wmd_schedule;
+
+typedef struct wmd_corpus wmd_corpus; /* opaque host object */
+
+/* ------------------------------------------------------------------ corpus */
+
+/* The target documents: the paper's V x N histogram matrix c (Section III-B-2),
+ * stored column by column (CSC, i.e. document-major), and the V x d word
+ * embedding table `vecs`. */
+typedef struct {
+  int64_t V;                /* vocabulary size, >= 1                                  */
+  int32_t d;                /* embedding width, 1..4096                               */
+  const float* emb;         /* device, V*d float32, row-major (word j = row j)        */
+  int64_t N;                /* number of target documents, >= 1                       */
+  int64_t nnz;              /* total (word, weight) entries, >= 0                     */
+  const int64_t* doc_ptr;   /* device, N+1 int64: doc k owns entries doc_ptr[k]..[k+1]*/
+  const int32_t* word_ids;  /* device, nnz int32 in [0, V); repeats are summed         */
+  const float* weights;     /* device, nnz float32, finite, >= 0; raw counts are fine:
+                               each document is normalised to sum 1 (Section III-B-1).
+                               A document whose weights sum to 0 scores NaN.            */
+  int32_t compact_vocab;    /* nonzero: evaluate the cost matrix only for the words
+                               that occur in the corpus (results are identical)        */
+  void* workspace;          /* device, >= wmd_corpus_workspace_bytes(); holds the
+                               normalised weights, compacted embeddings (f32 + bf16),
+                               squared norms and document-length buckets.  Borrowed.   */
+  size_t workspace_bytes;
+} wmd_corpus_desc;
+
+/* Bytes of corpus workspace needed for these sizes (0 on overflow). */
+size_t wmd_corpus_workspace_bytes(int64_t V, int32_t d, int64_t N, int64_t nnz);
+
+/* Validates the corpus on the device (ids in range, weights finite and >= 0,
+ * doc_ptr non-decreasing from 0 to nnz, at most 4096 entries per document),
+ * normalises every document, builds the compacted vocabulary and the
+ * document-length buckets.  Synchronises `stream` before returning.
+ * Invalid data -> WMD_ERR_INVALID_ARGUMENT and *out = NULL. */
+wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corpus** out);
+
+typedef struct {
+  int64_t V, N, nnz;
+  int32_t d, d_padded;      /* d_padded: row length of the internal embedding copies */
+  int64_t U;                /* vocabulary rows the cost matrix is evaluated on        */
+  int64_t empty_docs;       /* documents that score NaN (no positive weight)          */
+  int32_t n_buckets;        /* document-length buckets (capacity 16, 32, ... 4096)    */
+  int64_t bucket_docs[16];  /* documents per bucket                                   */
+  int32_t bucket_cap[16];   /* longest document a bucket holds                        */
+} wmd_corpus_info;
+
+wmd_status wmd_get_corpus_info(const wmd_corpus* c, wmd_corpus_info* info);
+
+/* Frees the host object and its cached launch plans.  NULL is a no-op.
+ * Borrowed device buffers are left to the caller. */
+wmd_status wmd_destroy(wmd_corpus* c);
+
+/* ----------------------------------------------------------------- queries */
+
+/* B query documents in one call.  Query b owns entries q_ptr[b]..q_ptr[b+1]
+ * of q_ids / q_weights; repeated ids are summed, zero weights dropped and
+ * the histogram normalised to 1 on the device (Algorithm 1, first step).
+ * The offsets are needed twice: on the host to plan the launches and on the
+ * device for the kernels; both copies must hold the same values. */
+typedef struct {
+  int32_t B;                  /* number of queries, >= 1                               */
+  const int64_t* q_ptr_host;  /* host, B+1, non-decreasing from 0; every query >= 1
+                                 entry and at most 2048 entries                        */
+  const int64_t* q_ptr;       /* device copy of q_ptr_host                             */
+  const int32_t* q_ids;       /* device, q_ptr[B] word ids                             */
+  const float* q_weights;     /* device, q_ptr[B] weights                              */
+  float lambda;               /* entropic weight, finite, > 0: K = exp(-lambda M)      */
+  int32_t max_iter;           /* Sinkhorn-Knopp iterations, 0..100000                  */
+  int32_t cdist;              /* wmd_cdist                                             */
+  int32_t schedule;           /* wmd_schedule                                          */
+} wmd_query_desc;
+
+/* Bytes of query workspace for B queries with these offsets and schedule
+ * (0 on invalid input).  Dominated by K^T and (K.*M)^T: 8 * U * sum_b S_b bytes,
+ * S_b = entries of query b rounded up to a multiple of 4. */
+size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* q_ptr_host,
+                                 int32_t schedule);
+
+/* Enqueues the whole hot path for B queries on `stream` and returns without
+ * waiting: query selection, cost matrix + K (one GEMM over all queries),
+ * the Sinkhorn iterations and the final pass.  `out` (device, B*N float32,
+ * row b = query b) is written when the stream reaches the end of the call.
+ * Host-side argument errors are reported synchronously.  Errors found on the
+ * device (a query id outside [0, V), a negative or non-finite weight, no
+ * positive weight) make that query's row NaN and are read back with
+ * wmd_query_errors().  Calls that share a workspace must be ordered on one
+ * stream; calls with separate workspaces may run concurrently. */
+wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/* Per-query device error codes of the last wmd_query on `workspace`
+ * (0 = ok, 1 = id out of range, 2 = bad weight, 3 = no positive weight).
+ * Copies B int32 into host `codes` and synchronises `stream`. */
+wmd_status wmd_query_errors(const void* workspace, int32_t B, int32_t* codes, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* wmd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMD_H */

@@ -1,0 +1,343 @@
+// Host runtime of the C ABI declared in include/wmd.h: argument validation,
+// workspace layout, corpus preparation and the launch sequence of a query.
+#include "wmd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wmd_internal.h"
+
+using namespace wmd;
+
+namespace {
+
+thread_local std::string g_err;
+
+wmd_status fail(wmd_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define WMD_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(WMD_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+template <class T>
+T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+bool mul_ok(size_t a, size_t b, size_t* out) {
+  if (a && b > SIZE_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+}  // namespace
+
+struct wmd_corpus {
+  int device = 0;
+  int64_t V = 0, N = 0, nnz = 0, U = 0;
+  int d = 0, dp = 0;
+  const float* emb = nullptr;
+  const int64_t* doc_ptr = nullptr;
+  CorpusLayout L{};
+  void* ws = nullptr;
+  // documents grouped by length bucket, then the NaN-scoring (empty) ones
+  int64_t bucket_off[kNumBuckets + 1] = {};
+  int64_t empty_off = 0, empty_count = 0;
+  int* docs() const { return at<int>(ws, L.docs); }
+};
+
+extern "C" {
+
+const char* wmd_last_error(void) { return g_err.c_str(); }
+
+size_t wmd_corpus_workspace_bytes(int64_t V, int32_t d, int64_t N, int64_t nnz) {
+  if (V < 1 || d < 1 || d > 4096 || N < 1 || nnz < 0) return 0;
+  size_t t;
+  if (!mul_ok((size_t)V, (size_t)padded_dim(d) * 6, &t)) return 0;
+  return CorpusLayout::make(V, d, N, nnz).total;
+}
+
+wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corpus** out) {
+  g_err.clear();
+  if (!out) return fail(WMD_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(WMD_ERR_INVALID_ARGUMENT, "desc is NULL");
+  const wmd_corpus_desc& D = *desc;
+  if (D.V < 1 || D.V > INT32_MAX - 1) return fail(WMD_ERR_INVALID_ARGUMENT, "V must be in [1, 2^31-2]");
+  if (D.d < 1 || D.d > 4096) return fail(WMD_ERR_INVALID_ARGUMENT, "d must be in [1, 4096]");
+  if (D.N < 1 || D.N > INT32_MAX) return fail(WMD_ERR_INVALID_ARGUMENT, "N must be in [1, 2^31-1]");
+  if (D.nnz < 0) return fail(WMD_ERR_INVALID_ARGUMENT, "nnz must be >= 0");
+  if (!D.emb || !D.doc_ptr || (D.nnz > 0 && (!D.word_ids || !D.weights)) || !D.workspace)
+    return fail(WMD_ERR_INVALID_ARGUMENT, "NULL device pointer in corpus descriptor");
+  const size_t need = wmd_corpus_workspace_bytes(D.V, D.d, D.N, D.nnz);
+  if (need == 0) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus sizes overflow");
+  if (D.workspace_bytes < need)
+    return fail(WMD_ERR_WORKSPACE_TOO_SMALL, "corpus workspace needs " + std::to_string(need) + " bytes");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // doc_ptr is needed on the host for validation and the length buckets
+  std::vector<int64_t> ptr((size_t)D.N + 1);
+  WMD_HIP(hipMemcpyAsync(ptr.data(), D.doc_ptr, sizeof(int64_t) * ptr.size(), hipMemcpyDeviceToHost, s));
+  WMD_HIP(hipStreamSynchronize(s));
+  if (ptr[0] != 0 || ptr[(size_t)D.N] != D.nnz)
+    return fail(WMD_ERR_INVALID_ARGUMENT, "doc_ptr must start at 0 and end at nnz");
+  for (int64_t k = 0; k < D.N; ++k) {
+    const int64_t len = ptr[(size_t)k + 1] - ptr[(size_t)k];
+    if (len < 0) return fail(WMD_ERR_INVALID_ARGUMENT, "doc_ptr must be non-decreasing");
+    if (len > kMaxDocLen)
+      return fail(WMD_ERR_NOT_SUPPORTED, "document " + std::to_string(k) + " has more than 4096 entries");
+  }
+
+  std::unique_ptr<wmd_corpus> c(new (std::nothrow) wmd_corpus());
+  if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "out of host memory");
+  WMD_HIP(hipGetDevice(&c->device));
+  c->V = D.V; c->N = D.N; c->nnz = D.nnz; c->d = D.d; c->dp = padded_dim(D.d);
+  c->emb = D.emb; c->doc_ptr = D.doc_ptr;
+  c->L = CorpusLayout::make(D.V, D.d, D.N, D.nnz);
+  c->ws = D.workspace;
+  const CorpusLayout& L = c->L;
+  void* ws = D.workspace;
+
+  int* err = at<int>(ws, L.err);
+  int* map = at<int>(ws, L.map);
+  WMD_HIP(launch_fill_i32(err, 64, 0, s));
+  WMD_HIP(launch_fill_i32(map, D.V + 1, D.compact_vocab ? 0 : 1, s));
+  if (D.nnz > 0) WMD_HIP(launch_prep_entries(D.word_ids, D.weights, D.nnz, D.V, D.compact_vocab ? map : at<int>(ws, L.used), err, s));
+  int herr = 0;
+  WMD_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  WMD_HIP(hipStreamSynchronize(s));
+  if (herr & 1) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus word id outside [0, V)");
+  if (herr & 2) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus weight negative or not finite");
+
+  WMD_HIP(launch_prep_docs(D.doc_ptr, D.weights, D.N, at<float>(ws, L.wn), at<int>(ws, L.dpos), s));
+  WMD_HIP(launch_prep_scan(map, D.V, s));
+  WMD_HIP(launch_prep_compact(map, D.V, at<int>(ws, L.used), D.word_ids, D.nnz, at<int>(ws, L.wl), s));
+  int U = 0;
+  WMD_HIP(hipMemcpyAsync(&U, map + D.V, sizeof(int), hipMemcpyDeviceToHost, s));
+  WMD_HIP(hipStreamSynchronize(s));
+  c->U = U;
+  if (U > 0)
+    WMD_HIP(launch_prep_emb(D.emb, D.d, c->dp, at<int>(ws, L.used), U, at<float>(ws, L.e32),
+                            at<uint16_t>(ws, L.e16), at<float>(ws, L.en), s));
+
+  // length buckets; documents with no positive weight go last and score NaN
+  std::vector<int> dpos((size_t)D.N);
+  WMD_HIP(hipMemcpyAsync(dpos.data(), at<int>(ws, L.dpos), sizeof(int) * dpos.size(), hipMemcpyDeviceToHost, s));
+  WMD_HIP(hipStreamSynchronize(s));
+  std::vector<std::vector<int>> lists(kNumBuckets + 1);
+  for (int64_t k = 0; k < D.N; ++k) {
+    const int64_t len = ptr[(size_t)k + 1] - ptr[(size_t)k];
+    if (len == 0 || !dpos[(size_t)k]) { lists[kNumBuckets].push_back((int)k); continue; }
+    int b = 0;
+    while (kBucketCap[b] < len) ++b;
+    lists[b].push_back((int)k);
+  }
+  std::vector<int> flat;
+  flat.reserve((size_t)D.N);
+  for (int b = 0; b <= kNumBuckets; ++b) {
+    if (b < kNumBuckets) c->bucket_off[b] = (int64_t)flat.size();
+    else c->empty_off = (int64_t)flat.size();
+    flat.insert(flat.end(), lists[b].begin(), lists[b].end());
+  }
+  c->bucket_off[kNumBuckets] = c->empty_off;
+  c->empty_count = (int64_t)lists[kNumBuckets].size();
+  WMD_HIP(hipMemcpyAsync(c->docs(), flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, s));
+  WMD_HIP(hipStreamSynchronize(s));
+  *out = c.release();
+  return WMD_OK;
+}
+
+wmd_status wmd_get_corpus_info(const wmd_corpus* c, wmd_corpus_info* info) {
+  g_err.clear();
+  if (!c || !info) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->V = c->V; info->N = c->N; info->nnz = c->nnz; info->d = c->d; info->d_padded = c->dp;
+  info->U = c->U; info->empty_docs = c->empty_count; info->n_buckets = kNumBuckets;
+  for (int b = 0; b < kNumBuckets; ++b) {
+    info->bucket_docs[b] = c->bucket_off[b + 1] - c->bucket_off[b];
+    info->bucket_cap[b] = kBucketCap[b];
+  }
+  return WMD_OK;
+}
+
+wmd_status wmd_destroy(wmd_corpus* c) {
+  g_err.clear();
+  delete c;
+  return WMD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct QueryPlan {
+  int B = 0;
+  int64_t C = 0;
+  std::vector<int64_t> col0, S;
+};
+
+wmd_status plan_query(const wmd_corpus* c, int32_t B, const int64_t* qp, QueryPlan* plan) {
+  if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
+  if (B < 1) return fail(WMD_ERR_INVALID_ARGUMENT, "B must be >= 1");
+  if (!qp) return fail(WMD_ERR_INVALID_ARGUMENT, "q_ptr_host is NULL");
+  if (qp[0] != 0) return fail(WMD_ERR_INVALID_ARGUMENT, "q_ptr must start at 0");
+  plan->B = B;
+  plan->col0.resize((size_t)B);
+  plan->S.resize((size_t)B);
+  int64_t C = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t n = qp[b + 1] - qp[b];
+    if (n < 1) return fail(WMD_ERR_INVALID_ARGUMENT, "query " + std::to_string(b) + " has no entries");
+    if (n > kMaxQueryLen)
+      return fail(WMD_ERR_NOT_SUPPORTED, "query " + std::to_string(b) + " has more than 2048 entries");
+    plan->col0[(size_t)b] = C;
+    plan->S[(size_t)b] = round4(n);
+    C += round4(n);
+  }
+  if (C > INT32_MAX / 2) return fail(WMD_ERR_NOT_SUPPORTED, "too many query words in one call");
+  plan->C = C;
+  return WMD_OK;
+}
+
+QueryLayout layout_for(const wmd_corpus* c, const QueryPlan& p, int schedule) {
+  const bool need_u = schedule == WMD_SCHEDULE_PER_ITERATION || schedule == WMD_SCHEDULE_UNFUSED;
+  const bool need_w = schedule == WMD_SCHEDULE_UNFUSED;
+  return QueryLayout::make(p.B, p.C, c->U, c->dp, c->N, c->nnz, need_u, need_w);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* q_ptr_host, int32_t schedule) {
+  g_err.clear();
+  QueryPlan plan;
+  if (plan_query(c, B, q_ptr_host, &plan) != WMD_OK) return 0;
+  if (schedule < WMD_SCHEDULE_AUTO || schedule > WMD_SCHEDULE_UNFUSED) return 0;
+  return layout_for(c, plan, schedule).total;
+}
+
+wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+  g_err.clear();
+  if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
+  if (!out || !workspace) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL output or workspace");
+  if (!q->q_ptr || !q->q_ids || !q->q_weights) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL device query pointer");
+  if (!(q->lambda > 0.f) || !std::isfinite(q->lambda)) return fail(WMD_ERR_INVALID_ARGUMENT, "lambda must be finite and > 0");
+  if (q->max_iter < 0 || q->max_iter > 100000) return fail(WMD_ERR_INVALID_ARGUMENT, "max_iter must be in [0, 100000]");
+  if (q->cdist != WMD_CDIST_FP32 && q->cdist != WMD_CDIST_BF16) return fail(WMD_ERR_INVALID_ARGUMENT, "unknown cdist precision");
+  if (q->schedule < WMD_SCHEDULE_AUTO || q->schedule > WMD_SCHEDULE_UNFUSED) return fail(WMD_ERR_INVALID_ARGUMENT, "unknown schedule");
+  QueryPlan plan;
+  wmd_status st = plan_query(c, q->B, q->q_ptr_host, &plan);
+  if (st != WMD_OK) return st;
+  const int schedule = q->schedule == WMD_SCHEDULE_AUTO ? WMD_SCHEDULE_RESIDENT : q->schedule;
+  const QueryLayout L = layout_for(c, plan, schedule);
+  if (workspace_bytes < L.total)
+    return fail(WMD_ERR_WORKSPACE_TOO_SMALL, "query workspace needs " + std::to_string(L.total) + " bytes");
+  int dev = 0;
+  WMD_HIP(hipGetDevice(&dev));
+  if (dev != c->device) return fail(WMD_ERR_INVALID_ARGUMENT, "current device differs from the corpus device");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = workspace;
+  const CorpusLayout& CL = c->L;
+
+  // a1: query selection and slot layout
+  SelectParams sp{};
+  sp.q_ptr = q->q_ptr; sp.q_ids = q->q_ids; sp.q_w = q->q_weights;
+  sp.B = q->B; sp.V = c->V; sp.d = c->d; sp.dp = c->dp; sp.emb = c->emb;
+  sp.err = at<int>(ws, L.err); sp.vr = at<int>(ws, L.vr); sp.qid = at<int>(ws, L.qid);
+  sp.r = at<float>(ws, L.r); sp.cinfo = at<int2>(ws, L.cinfo); sp.qn = at<float>(ws, L.qn);
+  sp.q32 = at<float>(ws, L.q32); sp.q16 = at<uint16_t>(ws, L.q16);
+  sp.want_bf16 = q->cdist == WMD_CDIST_BF16;
+  WMD_HIP(launch_select(sp, s));
+
+  // a2 + a3: cost matrix and K for every query word in one GEMM
+  float* kt = at<float>(ws, L.kt);
+  float* kmt = at<float>(ws, L.kmt);
+  if (c->U > 0) {
+    CdistParams cp{};
+    cp.e32 = at<float>(c->ws, CL.e32); cp.e16 = at<uint16_t>(c->ws, CL.e16); cp.en = at<float>(c->ws, CL.en);
+    cp.used = at<int>(c->ws, CL.used); cp.U = c->U;
+    cp.q32 = sp.q32; cp.q16 = sp.q16; cp.qn = sp.qn; cp.qid = sp.qid; cp.cinfo = sp.cinfo;
+    cp.C = plan.C; cp.dp = c->dp; cp.lam = q->lambda; cp.kt = kt; cp.kmt = kmt;
+    WMD_HIP(launch_cdist(cp, q->cdist == WMD_CDIST_BF16, s));
+  }
+
+  // a4-a6: Sinkhorn iterations and the final pass, per query and length bucket
+  float* ubuf = at<float>(ws, L.u);
+  float* wbuf = at<float>(ws, L.w);
+  for (int b = 0; b < q->B; ++b) {
+    const int64_t col0 = plan.col0[(size_t)b];
+    const int S = (int)plan.S[(size_t)b];
+    float* orow = out + (size_t)b * (size_t)c->N;
+    for (int bk = 0; bk < kNumBuckets; ++bk) {
+      const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
+      if (nd == 0) continue;
+      SinkConfig cfg{};
+      if (!choose_sink_config(S, kBucketCap[bk], &cfg))
+        return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
+                                               " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
+      SinkParams p{};
+      p.kt = kt + (size_t)col0 * (size_t)c->U;
+      p.kmt = kmt + (size_t)col0 * (size_t)c->U;
+      p.r = sp.r + col0;
+      p.vr = sp.vr + b;
+      p.doc_ptr = c->doc_ptr; p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);
+      p.docs = c->docs() + c->bucket_off[bk];
+      p.ndocs = (int)nd;
+      p.S = S;
+      p.out = orow;
+      p.u = ubuf + (size_t)col0 * (size_t)c->N;
+      p.w = wbuf + (size_t)b * (size_t)c->nnz;
+      const int grid = sink_grid(cfg, (int)nd);
+      if (schedule == WMD_SCHEDULE_RESIDENT) {
+        p.iters = q->max_iter; p.do_final = 1;
+        WMD_HIP(launch_sink(p, cfg, grid, s));
+      } else {
+        for (int it = 0; it < q->max_iter; ++it) {
+          if (schedule == WMD_SCHEDULE_PER_ITERATION) {
+            SinkParams a = p;
+            a.iters = 1; a.load_u = it > 0; a.store_u = 1;
+            WMD_HIP(launch_sink(a, cfg, grid, s));
+          } else {
+            SinkParams a = p;  // SDDMM: w_j = c_j / (K_j . u)
+            a.iters = 1; a.load_u = it > 0; a.store_w = 1;
+            WMD_HIP(launch_sink(a, cfg, grid, s));
+            SinkParams m = p;  // SpMM: acc = K w, u = r / acc
+            m.iters = 1; m.load_w = 1; m.store_u = 1;
+            WMD_HIP(launch_sink(m, cfg, grid, s));
+          }
+        }
+        SinkParams f = p;
+        f.iters = 0; f.load_u = q->max_iter > 0; f.do_final = 1;
+        WMD_HIP(launch_sink(f, cfg, grid, s));
+      }
+    }
+    if (c->empty_count > 0) WMD_HIP(launch_nan_docs(c->docs() + c->empty_off, c->empty_count, orow, s));
+  }
+  return WMD_OK;
+}
+
+wmd_status wmd_query_errors(const void* workspace, int32_t B, int32_t* codes, void* stream) {
+  g_err.clear();
+  if (!workspace || !codes || B < 1) return fail(WMD_ERR_INVALID_ARGUMENT, "bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  WMD_HIP(hipMemcpyAsync(codes, workspace, sizeof(int32_t) * (size_t)B, hipMemcpyDeviceToHost, s));
+  WMD_HIP(hipStreamSynchronize(s));
+  return WMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Cost matrix and Gibbs kernel for all queries of a call (Algorithm 1, first
+// line; Table I's cdist and exp).
+//
+// G = E_c Q^T on MFMA, with E_c the U x dp compacted vocabulary embeddings and
+// Q the C x dp query-word embeddings of every query (C = sum of padded query
+// widths).  The epilogue turns each G[t][n] into
+//     M = sqrt(max(0, |e_t|^2 + |q_n|^2 - 2 G)),  M = 0 when word t IS query word n,
+//     K = exp(-lambda M),
+// and stores K and K.*M transposed per query: row t of query b is S_b
+// contiguous floats, the row the fused SDDMM-SpMM gathers for every nonzero.
+//
+// FP32 inputs use v_mfma_f32_16x16x4_f32; BF16 inputs use gfx950's
+// v_mfma_f32_16x16x32_bf16; accumulation is float32 in both.  Both operands
+// are k-contiguous rows staged through LDS with double buffering.  Within one
+// instruction the assignment of k indices to lane groups is immaterial as long
+// as A and B use the same one, so each lane feeds a run of consecutive k
+// values read with one 16-byte LDS load.
+#include "lanes.h"
+#include "wmd_internal.h"
+
+namespace wmd {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN, int WM, bool BF16, int BK_>
+struct Tile {
+  static constexpr int WN = 4 / WM;
+  static constexpr int TM = BM / WM, TN = BN / WN;
+  static constexpr int FM = TM / 16, FN = TN / 16;
+  static constexpr int BK = BK_;                     // k elements per stage
+  static constexpr int ESZ = BF16 ? 2 : 4;           // bytes per element
+  static constexpr int PAD = 16 / ESZ;               // one 16-byte pad per row
+  static constexpr int LDK = BK + PAD;               // LDS row length (elements)
+  static constexpr int VEC = 16 / ESZ;               // elements per 16-byte load
+  static constexpr int NA = BM * BK / VEC / 256;     // 16-byte loads per thread
+  static constexpr int NB = BN * BK / VEC / 256;
+  static constexpr int VPR = BK / VEC;               // 16-byte loads per row
+  static constexpr size_t LDS = (size_t)2 * (BM + BN) * LDK * ESZ;
+  static_assert(FM >= 1 && FN >= 1 && NA >= 1 && NB >= 1, "tile");
+  static_assert(BM * BK % (VEC * 256) == 0 && BN * BK % (VEC * 256) == 0, "loads");
+  static_assert(BK % (BF16 ? 32 : 16) == 0 && 64 % BK == 0, "k step");
+  static_assert(LDS <= 65536, "lds");
+};
+
+template <int BM, int BN, int WM, bool BF16, int BK>
+__global__ void __launch_bounds__(256) cdist_kernel(CdistParams p) {
+  using T = Tile<BM, BN, WM, BF16, BK>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char* As = smem;
+  unsigned char* Bs = smem + (size_t)2 * BM * T::LDK * T::ESZ;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / T::WN, wn = wave % T::WN;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int64_t n0 = (int64_t)blockIdx.y * BN;
+  const unsigned char* Ag = BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32;
+  const unsigned char* Bg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
+  const size_t row_bytes = (size_t)p.dp * T::ESZ;
+
+  uint4 ra[T::NA], rb[T::NB];
+  auto load = [&](int kt) {
+    const size_t kb = (size_t)kt * T::BK * T::ESZ;
+#pragma unroll
+    for (int j = 0; j < T::NA; ++j) {
+      const int i = tid + 256 * j, row = i / T::VPR, v = i % T::VPR;
+      const int64_t g = m0 + row;
+      ra[j] = g < p.U ? *(const uint4*)(Ag + (size_t)g * row_bytes + kb + 16 * v) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < T::NB; ++j) {
+      const int i = tid + 256 * j, row = i / T::VPR, v = i % T::VPR;
+      const int64_t g = n0 + row;
+      rb[j] = g < p.C ? *(const uint4*)(Bg + (size_t)g * row_bytes + kb + 16 * v) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < T::NA; ++j) {
+      const int i = tid + 256 * j, row = i / T::VPR, v = i % T::VPR;
+      *(uint4*)(As + ((size_t)(buf * BM + row) * T::LDK) * T::ESZ + 16 * v) = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < T::NB; ++j) {
+      const int i = tid + 256 * j, row = i / T::VPR, v = i % T::VPR;
+      *(uint4*)(Bs + ((size_t)(buf * BN + row) * T::LDK) * T::ESZ + 16 * v) = rb[j];
+    }
+  };
+
+  f32x4 acc[T::FM][T::FN];
+#pragma unroll
+  for (int a = 0; a < T::FM; ++a)
+#pragma unroll
+    for (int b = 0; b < T::FN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = p.dp / T::BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+    const unsigned char* Ab = As + (size_t)cur * BM * T::LDK * T::ESZ;
+    const unsigned char* Bb = Bs + (size_t)cur * BN * T::LDK * T::ESZ;
+    if constexpr (!BF16) {
+#pragma unroll
+      for (int kk = 0; kk < T::BK / 16; ++kk) {
+        const int kofs = kk * 16 + 4 * (lane >> 4);
+        f32x4 av[T::FM], bv[T::FN];
+#pragma unroll
+        for (int a = 0; a < T::FM; ++a)
+          av[a] = *(const f32x4*)(Ab + ((size_t)(wm * T::TM + a * 16 + (lane & 15)) * T::LDK + kofs) * 4);
+#pragma unroll
+        for (int b = 0; b < T::FN; ++b)
+          bv[b] = *(const f32x4*)(Bb + ((size_t)(wn * T::TN + b * 16 + (lane & 15)) * T::LDK + kofs) * 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int a = 0; a < T::FM; ++a)
+#pragma unroll
+            for (int b = 0; b < T::FN; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][i], bv[b][i], acc[a][b], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < T::BK / 32; ++kk) {
+        const int kofs = kk * 32 + 8 * (lane >> 4);
+        bf16x8 av[T::FM], bv[T::FN];
+#pragma unroll
+        for (int a = 0; a < T::FM; ++a)
+          av[a] = *(const bf16x8*)(Ab + ((size_t)(wm * T::TM + a * 16 + (lane & 15)) * T::LDK + kofs) * 2);
+#pragma unroll
+        for (int b = 0; b < T::FN; ++b)
+          bv[b] = *(const bf16x8*)(Bb + ((size_t)(wn * T::TN + b * 16 + (lane & 15)) * T::LDK + kofs) * 2);
+#pragma unroll
+        for (int a = 0; a < T::FM; ++a)
+#pragma unroll
+          for (int b = 0; b < T::FN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue.  Accumulator register i of lane l holds row 4*(l/16)+i, column l%16
+  // of each 16x16 tile.
+#pragma unroll
+  for (int b = 0; b < T::FN; ++b) {
+    const int64_t n = n0 + wn * T::TN + b * 16 + (lane & 15);
+    if (n >= p.C) continue;
+    const int q = p.qid[n];
+    const float qn = p.qn[n];
+    const int2 ci = p.cinfo[n];
+    float* kt = p.kt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
+    float* kmt = p.kmt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
+#pragma unroll
+    for (int a = 0; a < T::FM; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t m = m0 + wm * T::TM + a * 16 + 4 * (lane >> 4) + i;
+        if (m >= p.U) continue;
+        float kv = 0.f, kmv = 0.f;
+        if (q >= 0) {
+          const float m2 = p.en[m] + qn - 2.f * acc[a][b][i];
+          const float dist = p.used[m] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
+          kv = expf(-p.lam * dist);
+          kmv = kv * dist;
+        }
+        kt[(size_t)m * ci.y] = kv;
+        kmt[(size_t)m * ci.y] = kmv;
+      }
+  }
+}
+
+template <int BM, int BN, int WM, bool BF16, int BK>
+hipError_t run(const CdistParams& p, hipStream_t s) {
+  using T = Tile<BM, BN, WM, BF16, BK>;
+  dim3 grid((unsigned)((p.U + BM - 1) / BM), (unsigned)((p.C + BN - 1) / BN));
+  cdist_kernel<BM, BN, WM, BF16, BK><<<grid, 256, T::LDS, s>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s) {
+  if (p.U <= 0 || p.C <= 0) return hipSuccess;
+  if (p.C <= 32) return bf16 ? run<64, 32, 4, true, 64>(p, s) : run<64, 32, 4, false, 32>(p, s);
+  if (p.C <= 64) return bf16 ? run<128, 64, 2, true, 64>(p, s) : run<128, 64, 2, false, 32>(p, s);
+  return bf16 ? run<128, 128, 2, true, 32>(p, s) : run<128, 128, 2, false, 16>(p, s);
+}
+
+}  // namespace wmd

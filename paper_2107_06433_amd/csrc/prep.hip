@@ -1,0 +1,254 @@
+// Corpus preparation (run once by wmd_create_corpus) and query selection
+// (the first step of every wmd_query).
+#include "lanes.h"
+#include "wmd_internal.h"
+
+namespace wmd {
+
+namespace {
+
+__global__ void fill_i32_kernel(int* p, int64_t n, int value) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// Validate every (word, weight) entry and mark the words that occur.
+__global__ void prep_entries_kernel(const int32_t* ids, const float* w, int64_t nnz, int64_t V,
+                                    int* flags, int* err) {
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t id = ids[e];
+    const float x = w[e];
+    if (id < 0 || id >= V) bad |= 1;
+    else flags[id] = 1;
+    if (!(x >= 0.f) || isinf(x)) bad |= 2;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// Normalise each document to sum 1 (Section III-B-1).  The sum is taken in
+// double and each weight is divided in double before rounding to float.
+__global__ void prep_docs_kernel(const int64_t* doc_ptr, const float* w, int64_t N, float* wn, int* dpos) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = doc_ptr[k], e = doc_ptr[k + 1];
+    double s = 0.0;
+    for (int64_t j = b; j < e; ++j) s += (double)w[j];
+    dpos[k] = s > 0.0;
+    for (int64_t j = b; j < e; ++j) wn[j] = s > 0.0 ? (float)((double)w[j] / s) : 0.f;
+  }
+}
+
+// Exclusive prefix sum of flags[0..V) in place; map[V] = total.  One block.
+__global__ void __launch_bounds__(1024) prep_scan_kernel(int* map, int64_t V) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (V + 1023) / 1024;
+  const int64_t b = t * chunk, e = b + chunk < V ? b + chunk : V;
+  int s = 0;
+  for (int64_t i = b; i < e; ++i) s += map[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;  // exclusive
+  for (int64_t i = b; i < e; ++i) {
+    int f = map[i];
+    map[i] = run;
+    run += f;
+  }
+  if (t == 1023) map[V] = part[1023];
+}
+
+__global__ void prep_compact_kernel(const int* map, int64_t V, int* used, const int32_t* ids, int64_t nnz, int* wl) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < V; v += stride)
+    if (map[v + 1] > map[v]) used[map[v]] = (int)v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += stride) wl[e] = map[ids[e]];
+}
+
+// One wave per compacted row: zero-padded f32 and bf16 copies and |e|^2.
+__global__ void prep_emb_kernel(const float* emb, int d, int dp, const int* used, int64_t U,
+                                float* e32, uint16_t* e16, float* en) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); row < U; row += waves) {
+    const float* src = emb + (size_t)used[row] * d;
+    double s = 0.0;
+    for (int t = lane; t < dp; t += 64) {
+      const float x = t < d ? src[t] : 0.f;
+      e32[(size_t)row * dp + t] = x;
+      e16[(size_t)row * dp + t] = f32_to_bf16(x);
+      s += (double)x * (double)x;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) en[row] = (float)s;
+  }
+}
+
+// Algorithm 1, first step, for one query per block: validate the entries,
+// sum repeated ids, drop zero weights, normalise r in double, and lay out the
+// query's S slots (S = entries rounded up to 4) of the GEMM's column space:
+// word id, r, the query's column base and width, the f32/bf16 embedding row
+// and its squared norm.  Slots past the selected words get id -1, r = 0.
+__global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
+  __shared__ int s_id[kMaxQueryLen];
+  __shared__ float s_w[kMaxQueryLen];
+  __shared__ double s_m[kMaxQueryLen];
+  __shared__ int s_pos[kMaxQueryLen];
+  __shared__ long long s_red[256];
+  __shared__ double s_dred[256];
+  __shared__ int s_err;
+  const int b = blockIdx.x;
+  const int t = threadIdx.x;
+  const int64_t beg = p.q_ptr[b];
+  const int n = (int)(p.q_ptr[b + 1] - beg);
+  // column base of this query: sum of the padded widths of the queries before it
+  long long part = 0;
+  for (int bb = t; bb < b; bb += 256) part += (p.q_ptr[bb + 1] - p.q_ptr[bb] + 3) & ~3LL;
+  s_red[t] = part;
+  if (t == 0) s_err = 0;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) s_red[t] += s_red[t + off];
+    __syncthreads();
+  }
+  const int64_t col0 = s_red[0];
+  const int S = (n + 3) & ~3;
+  const int nn = n < kMaxQueryLen ? n : kMaxQueryLen;
+  for (int i = t; i < nn; i += 256) {
+    const int id = p.q_ids[beg + i];
+    const float x = p.q_w[beg + i];
+    s_id[i] = id;
+    s_w[i] = x;
+    if (id < 0 || id >= p.V) atomicOr(&s_err, 1);
+    if (!(x >= 0.f) || isinf(x)) atomicOr(&s_err, 2);
+  }
+  __syncthreads();
+  // merge repeats into their first occurrence, summing in entry order
+  for (int i = t; i < nn; i += 256) {
+    const int id = s_id[i];
+    bool first = true;
+    for (int j = 0; j < i; ++j)
+      if (s_id[j] == id) { first = false; break; }
+    double m = 0.0;
+    if (first)
+      for (int j = i; j < nn; ++j)
+        if (s_id[j] == id) m += (double)s_w[j];
+    s_m[i] = first ? m : 0.0;
+  }
+  __syncthreads();
+  // slot of every selected entry, in entry order; total weight in a fixed order
+  if (t == 0) {
+    int c = 0;
+    double tot = 0.0;
+    for (int i = 0; i < nn; ++i) {
+      if (s_m[i] > 0.0) { s_pos[i] = c++; tot += s_m[i]; }
+      else s_pos[i] = -1;
+    }
+    s_red[0] = c;
+    s_dred[0] = tot;
+    if (n > kMaxQueryLen) s_err |= 4;
+    if (s_err == 0 && c == 0) s_err = 8;
+  }
+  __syncthreads();
+  const int err = s_err;
+  const int vr = err ? 0 : (int)s_red[0];
+  const double tot = s_dred[0];
+  if (t == 0) {
+    p.err[b] = err & 1 ? 1 : err & 2 ? 2 : err & 4 ? 4 : err & 8 ? 3 : 0;
+    p.vr[b] = vr;
+  }
+  for (int s = t; s < S; s += 256) {
+    p.qid[col0 + s] = -1;
+    p.r[col0 + s] = 0.f;
+    p.cinfo[col0 + s] = make_int2((int)col0, S);
+  }
+  __syncthreads();
+  if (vr > 0)
+    for (int i = t; i < nn; i += 256)
+      if (s_pos[i] >= 0) {
+        p.qid[col0 + s_pos[i]] = s_id[i];
+        p.r[col0 + s_pos[i]] = (float)(s_m[i] / tot);
+      }
+  __syncthreads();
+  // embedding rows of the slots (one wave per slot)
+  const int lane = t & 63;
+  for (int s = t >> 6; s < S; s += 4) {
+    const int q = p.qid[col0 + s];
+    const float* src = p.emb + (size_t)(q < 0 ? 0 : q) * p.d;
+    double nrm = 0.0;
+    for (int k = lane; k < p.dp; k += 64) {
+      const float x = (q >= 0 && k < p.d) ? src[k] : 0.f;
+      p.q32[(size_t)(col0 + s) * p.dp + k] = x;
+      if (p.want_bf16) p.q16[(size_t)(col0 + s) * p.dp + k] = f32_to_bf16(x);
+      nrm += (double)x * (double)x;
+    }
+    for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off);
+    if (lane == 0) p.qn[col0 + s] = (float)nrm;
+  }
+}
+
+__global__ void nan_docs_kernel(const int* docs, int64_t ndocs, float* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ndocs; i += (int64_t)gridDim.x * blockDim.x)
+    out[docs[i]] = __int_as_float(0x7FC00000);
+}
+
+inline int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t s) {
+  fill_i32_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_entries(const int32_t* ids, const float* w, int64_t nnz, int64_t V, int* flags,
+                               int* err, hipStream_t s) {
+  prep_entries_kernel<<<grid_for(nnz, 256), 256, 0, s>>>(ids, w, nnz, V, flags, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_docs(const int64_t* doc_ptr, const float* w, int64_t N, float* wn, int* dpos,
+                            hipStream_t s) {
+  prep_docs_kernel<<<grid_for(N, 256), 256, 0, s>>>(doc_ptr, w, N, wn, dpos);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_scan(int* map, int64_t V, hipStream_t s) {
+  prep_scan_kernel<<<1, 1024, 0, s>>>(map, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_compact(const int* map, int64_t V, int* used, const int32_t* ids, int64_t nnz, int* wl,
+                               hipStream_t s) {
+  prep_compact_kernel<<<grid_for(V > nnz ? V : nnz, 256), 256, 0, s>>>(map, V, used, ids, nnz, wl);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_emb(const float* emb, int d, int dp, const int* used, int64_t U, float* e32,
+                           uint16_t* e16, float* en, hipStream_t s) {
+  prep_emb_kernel<<<grid_for(U, 4), 256, 0, s>>>(emb, d, dp, used, U, e32, e16, en);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectParams& p, hipStream_t s) {
+  select_kernel<<<p.B, 256, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_nan_docs(const int* docs, int64_t ndocs, float* out, hipStream_t s) {
+  if (ndocs <= 0) return hipSuccess;
+  nan_docs_kernel<<<grid_for(ndocs, 256), 256, 0, s>>>(docs, ndocs, out);
+  return hipGetLastError();
+}
+
+}  // namespace wmd

@@ -1,0 +1,138 @@
+// Private declarations shared by the host runtime (capi.cpp) and the kernel
+// translation units.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wmd {
+
+constexpr int kMaxDocLen = 4096;     // longest document the fused kernels hold
+constexpr int kMaxQueryLen = 2048;   // raw entries per query
+constexpr int kNumBuckets = 9;       // document-length capacities 16 .. 4096
+constexpr int kBucketCap[kNumBuckets] = {16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t round4(int64_t x) { return (x + 3) & ~int64_t(3); }
+// Row length of the internal embedding copies: a multiple of both GEMM k-steps.
+inline int padded_dim(int d) { return (d + 63) / 64 * 64; }
+
+// ---------------------------------------------------------------- layouts
+
+// Corpus workspace: derived arrays built once by wmd_create_corpus.
+struct CorpusLayout {
+  size_t err, wn, wl, map, used, dpos, docs, en, e32, e16, total;
+  static CorpusLayout make(int64_t V, int d, int64_t N, int64_t nnz) {
+    CorpusLayout L{};
+    const int dp = padded_dim(d);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+    L.err = take(64 * sizeof(int));
+    L.wn = take(sizeof(float) * (size_t)nnz);           // normalised weights
+    L.wl = take(sizeof(int) * (size_t)nnz);             // compacted word ids
+    L.map = take(sizeof(int) * (size_t)(V + 1));        // vocab id -> compacted row
+    L.used = take(sizeof(int) * (size_t)V);             // compacted row -> vocab id
+    L.dpos = take(sizeof(int) * (size_t)N);             // doc has positive mass
+    L.docs = take(sizeof(int) * (size_t)N);             // docs grouped by length bucket
+    L.en = take(sizeof(float) * (size_t)V);             // |e|^2 of compacted rows
+    L.e32 = take(sizeof(float) * (size_t)V * dp);       // compacted embeddings, f32
+    L.e16 = take(sizeof(uint16_t) * (size_t)V * dp);    // same, bf16
+    L.total = o;
+    return L;
+  }
+};
+
+// Query workspace: everything one wmd_query call writes.  The per-query error
+// codes sit at offset 0 so that wmd_query_errors() can find them from the
+// workspace pointer alone.
+struct QueryLayout {
+  size_t err, vr, qid, r, cinfo, qn, q32, q16, kt, kmt, u, w, total;
+  static QueryLayout make(int B, int64_t C, int64_t U, int dp, int64_t N, int64_t nnz,
+                          bool need_u, bool need_w) {
+    QueryLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+    L.err = take(sizeof(int) * (size_t)B);
+    L.vr = take(sizeof(int) * (size_t)B);
+    L.qid = take(sizeof(int) * (size_t)C);
+    L.r = take(sizeof(float) * (size_t)C);
+    L.cinfo = take(sizeof(int2) * (size_t)C);
+    L.qn = take(sizeof(float) * (size_t)C);
+    L.q32 = take(sizeof(float) * (size_t)C * dp);
+    L.q16 = take(sizeof(uint16_t) * (size_t)C * dp);
+    L.kt = take(sizeof(float) * (size_t)C * (size_t)U);
+    L.kmt = take(sizeof(float) * (size_t)C * (size_t)U);
+    L.u = need_u ? take(sizeof(float) * (size_t)C * (size_t)N) : o;
+    L.w = need_w ? take(sizeof(float) * (size_t)nnz * (size_t)B) : o;
+    L.total = o;
+    return L;
+  }
+};
+
+// ------------------------------------------------------- kernel parameters
+
+struct SelectParams {
+  const int64_t* q_ptr; const int32_t* q_ids; const float* q_w;
+  int B; int64_t V; int d; int dp;
+  const float* emb;
+  int* err; int* vr; int* qid; float* r; int2* cinfo; float* qn; float* q32; uint16_t* q16;
+  int want_bf16;
+};
+
+struct CdistParams {
+  const float* e32; const uint16_t* e16; const float* en; const int* used; int64_t U;
+  const float* q32; const uint16_t* q16; const float* qn; const int* qid; const int2* cinfo;
+  int64_t C; int dp; float lam;
+  float* kt; float* kmt;
+};
+
+// One fused SDDMM-SpMM launch over the documents of one length bucket for one
+// query.  The same kernel runs every schedule; flags pick the variant.
+struct SinkParams {
+  const float* kt;        // K^T block of the query: U rows x S floats
+  const float* kmt;       // (K .* M)^T block, same shape
+  const float* r;         // S slots of the normalised query histogram (0 = unused slot)
+  const int* vr;          // device: number of used slots (0 = invalid query)
+  const int64_t* doc_ptr; const int* wl; const float* wn;
+  const int* docs; int ndocs;
+  int S;
+  float* out;             // row of this query, indexed by document id
+  float* u;               // N x S scalings (per-iteration schedules), doc-major
+  float* w;               // nnz sparse intermediate (unfused schedule)
+  int iters;              // iterations run by this launch
+  int load_u, store_u, do_final, store_w, load_w;
+  int lg_cg, lg_l;        // lane grid: 2^lg_cg column lanes, 2^lg_l lanes per document
+};
+
+// Register-resident shape (tc x tr cells per lane, lane grid 2^lg_cg x 2^(lg_l-lg_cg),
+// multiwave = more than 64 lanes per item) or, with `stream`, the one-block-per-item
+// fallback that re-reads K^T rows on every pass.
+struct SinkConfig { int tc, tr, lg_cg, lg_l; bool multiwave; bool stream; };
+
+// --------------------------------------------------------- launch wrappers
+// Each returns the hipError_t of its launch.
+
+hipError_t launch_fill_i32(int* p, int64_t n, int value, hipStream_t s);
+hipError_t launch_prep_entries(const int32_t* ids, const float* w, int64_t nnz, int64_t V,
+                               int* flags, int* err, hipStream_t s);
+hipError_t launch_prep_docs(const int64_t* doc_ptr, const float* w, int64_t N, float* wn,
+                            int* dpos, hipStream_t s);
+hipError_t launch_prep_scan(int* map, int64_t V, hipStream_t s);
+hipError_t launch_prep_compact(const int* map, int64_t V, int* used, const int32_t* ids,
+                               int64_t nnz, int* wl, hipStream_t s);
+hipError_t launch_prep_emb(const float* emb, int d, int dp, const int* used, int64_t U,
+                           float* e32, uint16_t* e16, float* en, hipStream_t s);
+
+hipError_t launch_select(const SelectParams& p, hipStream_t s);
+hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s);
+hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s);
+hipError_t launch_nan_docs(const int* docs, int64_t ndocs, float* out, hipStream_t s);
+
+// Host-side config choice for one (padded query width, bucket capacity) pair.
+bool choose_sink_config(int S, int cap, SinkConfig* cfg);
+bool sink_config_supported(const SinkConfig& cfg);
+int sink_grid(const SinkConfig& cfg, int ndocs);
+int sink_block(const SinkConfig& cfg);
+
+}  // namespace wmd

@@ -1,0 +1,242 @@
+"""Python binding of libwmd.so (the C ABI in include/wmd.h).
+
+Argument marshalling only: this module turns torch tensors into device
+pointers and the current HIP stream into a handle, allocates the workspaces the
+library asks for (torch owns all device memory), and calls the library.  Every
+step of the computation runs in the library's HIP kernels.  If the shared
+library is missing the import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwmd.so")
+
+WMD_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "device error", 4: "not supported"}
+CDIST = {"fp32": 0, "bf16": 1}
+SCHEDULE = {"auto": 0, "resident": 1, "per_iteration": 2, "unfused": 3}
+QUERY_ERRORS = {0: "ok", 1: "query word id out of range", 2: "query weight negative or not finite",
+                3: "query has no positive weight", 4: "query too long"}
+
+EXPORTS = [
+    "wmd_corpus_workspace_bytes", "wmd_create_corpus", "wmd_get_corpus_info", "wmd_destroy",
+    "wmd_query_workspace_bytes", "wmd_query", "wmd_query_errors", "wmd_last_error",
+]
+
+
+class CorpusDesc(ctypes.Structure):
+    _fields_ = [
+        ("V", ctypes.c_int64), ("d", ctypes.c_int32), ("emb", ctypes.c_void_p),
+        ("N", ctypes.c_int64), ("nnz", ctypes.c_int64), ("doc_ptr", ctypes.c_void_p),
+        ("word_ids", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+        ("compact_vocab", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class CorpusInfo(ctypes.Structure):
+    _fields_ = [
+        ("V", ctypes.c_int64), ("N", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("d", ctypes.c_int32), ("d_padded", ctypes.c_int32), ("U", ctypes.c_int64),
+        ("empty_docs", ctypes.c_int64), ("n_buckets", ctypes.c_int32),
+        ("bucket_docs", ctypes.c_int64 * 16), ("bucket_cap", ctypes.c_int32 * 16),
+    ]
+
+
+class QueryDesc(ctypes.Structure):
+    _fields_ = [
+        ("B", ctypes.c_int32), ("q_ptr_host", ctypes.c_void_p), ("q_ptr", ctypes.c_void_p),
+        ("q_ids", ctypes.c_void_p), ("q_weights", ctypes.c_void_p), ("lam", ctypes.c_float),
+        ("max_iter", ctypes.c_int32), ("cdist", ctypes.c_int32), ("schedule", ctypes.c_int32),
+    ]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2107_06433_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.wmd_corpus_workspace_bytes.argtypes = [i64, i32, i64, i64]
+    lib.wmd_corpus_workspace_bytes.restype = sz
+    lib.wmd_create_corpus.argtypes = [ctypes.POINTER(CorpusDesc), vp, ctypes.POINTER(vp)]
+    lib.wmd_create_corpus.restype = i32
+    lib.wmd_get_corpus_info.argtypes = [vp, ctypes.POINTER(CorpusInfo)]
+    lib.wmd_get_corpus_info.restype = i32
+    lib.wmd_destroy.argtypes = [vp]
+    lib.wmd_destroy.restype = i32
+    lib.wmd_query_workspace_bytes.argtypes = [vp, i32, vp, i32]
+    lib.wmd_query_workspace_bytes.restype = sz
+    lib.wmd_query.argtypes = [vp, ctypes.POINTER(QueryDesc), vp, vp, sz, vp]
+    lib.wmd_query.restype = i32
+    lib.wmd_query_errors.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.wmd_query_errors.restype = i32
+    lib.wmd_last_error.argtypes = []
+    lib.wmd_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_LIB: ctypes.CDLL | None = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class WMDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != WMD_OK:
+        raise WMDError(status, lib().wmd_last_error().decode())
+
+
+def _stream_handle(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class QueryBatch:
+    """Queries marshalled for the library: offsets on host and device, ids and weights on device."""
+    q_ptr_host: np.ndarray      # int64 [B+1]
+    q_ptr: torch.Tensor         # int64 [B+1], device
+    ids: torch.Tensor           # int32 [T], device
+    weights: torch.Tensor       # float32 [T], device
+
+    @property
+    def B(self) -> int:
+        return len(self.q_ptr_host) - 1
+
+    @staticmethod
+    def from_arrays(q_ptr, ids, weights, device="cuda") -> "QueryBatch":
+        q_ptr = np.ascontiguousarray(np.asarray(q_ptr, dtype=np.int64))
+        return QueryBatch(
+            q_ptr_host=q_ptr,
+            q_ptr=torch.from_numpy(q_ptr).to(device),
+            ids=torch.as_tensor(np.asarray(ids, dtype=np.int32)).to(device),
+            weights=torch.as_tensor(np.asarray(weights, dtype=np.float32)).to(device),
+        )
+
+    @staticmethod
+    def from_list(queries, device="cuda") -> "QueryBatch":
+        lens = [len(q[0]) for q in queries]
+        ptr = np.zeros(len(queries) + 1, dtype=np.int64)
+        ptr[1:] = np.cumsum(lens)
+        ids = np.concatenate([np.asarray(q[0], dtype=np.int32) for q in queries])
+        w = np.concatenate([np.asarray(q[1], dtype=np.float32) for q in queries])
+        return QueryBatch.from_arrays(ptr, ids, w, device)
+
+
+class Corpus:
+    """A resident corpus: embeddings (V x d) and documents in CSC form, on one GPU."""
+
+    def __init__(self, emb: torch.Tensor, doc_ptr: torch.Tensor, word_ids: torch.Tensor,
+                 weights: torch.Tensor, compact_vocab: bool = True, stream=None):
+        if not emb.is_cuda:
+            raise ValueError("emb must be a device tensor")
+        self.emb = emb.contiguous().to(torch.float32)
+        self.doc_ptr = doc_ptr.contiguous().to(device=emb.device, dtype=torch.int64)
+        self.word_ids = word_ids.contiguous().to(device=emb.device, dtype=torch.int32)
+        self.weights = weights.contiguous().to(device=emb.device, dtype=torch.float32)
+        self.device = emb.device
+        V, d = self.emb.shape
+        N = self.doc_ptr.numel() - 1
+        nnz = self.word_ids.numel()
+        nbytes = lib().wmd_corpus_workspace_bytes(V, d, N, nnz)
+        if nbytes == 0:
+            raise WMDError(1, "invalid corpus sizes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=emb.device)
+        desc = CorpusDesc(V=V, d=d, emb=_ptr(self.emb), N=N, nnz=nnz, doc_ptr=_ptr(self.doc_ptr),
+                          word_ids=_ptr(self.word_ids), weights=_ptr(self.weights),
+                          compact_vocab=1 if compact_vocab else 0,
+                          workspace=_ptr(self.workspace), workspace_bytes=nbytes)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().wmd_create_corpus(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(handle)))
+        self._h = handle
+        self.V, self.d, self.N, self.nnz = V, d, N, nnz
+
+    @classmethod
+    def from_numpy(cls, emb, doc_ptr, word_ids, weights, device="cuda", compact_vocab=True):
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        return cls(t(emb, torch.float32), t(doc_ptr, torch.int64), t(word_ids, torch.int32),
+                   t(weights, torch.float32), compact_vocab=compact_vocab)
+
+    def info(self) -> dict:
+        info = CorpusInfo()
+        _check(lib().wmd_get_corpus_info(self._h, ctypes.byref(info)))
+        nb = info.n_buckets
+        return dict(V=info.V, N=info.N, nnz=info.nnz, d=info.d, d_padded=info.d_padded, U=info.U,
+                    empty_docs=info.empty_docs, bucket_docs=list(info.bucket_docs[:nb]),
+                    bucket_cap=list(info.bucket_cap[:nb]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wmd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, batch: QueryBatch, schedule: str = "auto") -> int:
+        n = lib().wmd_query_workspace_bytes(self._h, batch.B, batch.q_ptr_host.ctypes.data,
+                                            SCHEDULE[schedule])
+        if n == 0:
+            raise WMDError(1, lib().wmd_last_error().decode() or "invalid query batch")
+        return n
+
+    def query(self, batch: QueryBatch, lam: float, max_iter: int, cdist: str = "fp32",
+              schedule: str = "auto", out: torch.Tensor | None = None,
+              workspace: torch.Tensor | None = None, stream=None, check: bool = True) -> torch.Tensor:
+        """Distances of every query to every document: float32 [B, N] on the device.
+
+        With ``check`` the call waits for the stream and raises ValueError if a
+        query held an invalid id or weight (its row is NaN either way).
+        """
+        B = batch.B
+        if out is None:
+            out = torch.empty((B, self.N), dtype=torch.float32, device=self.device)
+        need = self.workspace_bytes(batch, schedule)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        desc = QueryDesc(B=B, q_ptr_host=batch.q_ptr_host.ctypes.data, q_ptr=_ptr(batch.q_ptr),
+                         q_ids=_ptr(batch.ids), q_weights=_ptr(batch.weights), lam=float(lam),
+                         max_iter=int(max_iter), cdist=CDIST[cdist], schedule=SCHEDULE[schedule])
+        sh = _stream_handle(stream)
+        with torch.cuda.device(self.device):
+            _check(lib().wmd_query(self._h, ctypes.byref(desc), _ptr(out), _ptr(workspace),
+                                   workspace.numel(), sh))
+        self.last_workspace = workspace
+        if check:
+            codes = self.query_errors(workspace, B, stream)
+            bad = [(b, QUERY_ERRORS.get(int(c), int(c))) for b, c in enumerate(codes) if c]
+            if bad:
+                raise ValueError(f"invalid queries: {bad[:8]}")
+        return out
+
+    def query_errors(self, workspace: torch.Tensor, B: int, stream=None) -> np.ndarray:
+        codes = np.zeros(B, dtype=np.int32)
+        _check(lib().wmd_query_errors(_ptr(workspace), B,
+                                      codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      _stream_handle(stream)))
+        return codes

@@ -1,0 +1,299 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: float32 cost matrix and iteration within 1e-4 relative of the
+oracle; bf16 cost-matrix GEMM within 1e-3; both as |g - o| <= tol |o| + 1e-7
+(the absolute floor only matters for identical documents, whose distance is
+near zero).  Integer outputs (error codes) and NaN placement are exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.distance import cdist
+
+import oracle
+from paper_2107_06433_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+TOL16 = 1e-3
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2107_06433_amd import wmd  # loads libwmd.so; fails loudly if missing
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return wmd
+
+
+def rel_err(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    return np.abs(g - o) / (np.abs(o) + 1e-7 / TOL32)
+
+
+def assert_close(g, o, tol, what=""):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    assert g.shape == o.shape
+    nan_g, nan_o = np.isnan(g), np.isnan(o)
+    assert np.array_equal(nan_g, nan_o), f"{what}: NaN placement differs"
+    ok = ~nan_o
+    err = np.abs(g[ok] - o[ok])
+    lim = tol * np.abs(o[ok]) + 1e-7
+    bad = np.nonzero(err > lim)[0]
+    assert bad.size == 0, (f"{what}: {bad.size} of {ok.sum()} outside tol {tol}; worst rel "
+                           f"{(err / np.abs(o[ok])).max():.3e}")
+
+
+def corpus_of(W, c, compact=True):
+    return W.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, c.weights, compact_vocab=compact)
+
+
+def run(W, corpus, queries, lam, iters, **kw):
+    batch = W.QueryBatch.from_arrays(queries.q_ptr, queries.ids, queries.weights)
+    out = corpus.query(batch, lam, iters, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_support(c, ids, qw, lam, iters, docs=None):
+    return oracle.sinkhorn_wmd_support(c.emb, c.doc_ptr, c.word_ids, c.weights, ids, qw, lam, iters, docs=docs)
+
+
+# ---------------------------------------------------------------- tiny workload
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.make_workload("tiny")
+    ids, qw = w.queries.query(0)
+    ref = oracle.wmd_dense_corpus(w.corpus.emb, w.corpus.doc_ptr, w.corpus.word_ids, w.corpus.weights,
+                                  ids, qw, w.lam, w.max_iter)
+    return w, ref
+
+
+@pytest.mark.parametrize("schedule", ["resident", "per_iteration", "unfused"])
+def test_tiny_fp32_matches_dense_oracle(W, tiny, schedule):
+    w, ref = tiny
+    got = run(W, corpus_of(W, w.corpus), w.queries, w.lam, w.max_iter, schedule=schedule)[0]
+    assert_close(got, ref, TOL32, schedule)
+
+
+def test_tiny_bf16_matches_dense_oracle(W, tiny):
+    w, ref = tiny
+    got = run(W, corpus_of(W, w.corpus), w.queries, w.lam, w.max_iter, cdist="bf16")[0]
+    assert_close(got, ref, TOL16, "bf16")
+
+
+def test_vocab_compaction_changes_nothing(W, tiny):
+    w, _ = tiny
+    a = run(W, corpus_of(W, w.corpus, compact=True), w.queries, w.lam, w.max_iter)
+    b = run(W, corpus_of(W, w.corpus, compact=False), w.queries, w.lam, w.max_iter)
+    assert np.array_equal(a, b)
+
+
+def test_deterministic_and_schedules_agree(W, tiny):
+    w, _ = tiny
+    c = corpus_of(W, w.corpus)
+    a = run(W, c, w.queries, w.lam, w.max_iter)
+    b = run(W, c, w.queries, w.lam, w.max_iter)
+    assert np.array_equal(a, b)
+    p = run(W, c, w.queries, w.lam, w.max_iter, schedule="per_iteration")
+    assert np.array_equal(a, p), "resident and per-iteration schedules run the same arithmetic"
+
+
+@pytest.mark.parametrize("iters", [0, 1, 2, 40])
+def test_iteration_counts(W, tiny, iters):
+    w, _ = tiny
+    ids, qw = w.queries.query(0)
+    ref = oracle.wmd_dense_corpus(w.corpus.emb, w.corpus.doc_ptr, w.corpus.word_ids, w.corpus.weights,
+                                  ids, qw, w.lam, iters)
+    got = run(W, corpus_of(W, w.corpus), w.queries, w.lam, iters)[0]
+    assert_close(got, ref, TOL32, f"iters={iters}")
+
+
+# ------------------------------------------------------------ single-query size
+
+@pytest.fixture(scope="module")
+def single():
+    return synth.make_workload("single")
+
+
+@pytest.fixture(scope="module")
+def single_run(W, single):
+    c = corpus_of(W, single.corpus)
+    g32 = run(W, c, single.queries, single.lam, single.max_iter)[0]
+    g16 = run(W, c, single.queries, single.lam, single.max_iter, cdist="bf16")[0]
+    return c, g32, g16
+
+
+SAMPLE = 240
+
+
+def sample_docs(N, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(N, size=min(SAMPLE, N), replace=False))
+
+
+def test_single_fp32_sampled(W, single, single_run):
+    _, g32, _ = single_run
+    docs = sample_docs(single.corpus.N)
+    ids, qw = single.queries.query(0)
+    ref = oracle_support(single.corpus, ids, qw, single.lam, single.max_iter, docs)
+    assert_close(g32[docs], ref, TOL32, "single fp32")
+
+
+def test_single_bf16_sampled(W, single, single_run):
+    _, _, g16 = single_run
+    docs = sample_docs(single.corpus.N, seed=1)
+    ids, qw = single.queries.query(0)
+    ref = oracle_support(single.corpus, ids, qw, single.lam, single.max_iter, docs)
+    assert_close(g16[docs], ref, TOL16, "single bf16")
+
+
+def test_single_every_document_within_cost_range(W, single, single_run):
+    """At any size: d_k is a convex combination of the costs between the
+    query's words and document k's words (the plan has total mass 1)."""
+    _, g32, _ = single_run
+    c = single.corpus
+    ids, qw = single.queries.query(0)
+    sel, _ = oracle.select_query(c.V, ids, qw)
+    Eq = c.emb[sel].astype(np.float64)
+    for k in range(c.N):
+        wk = c.word_ids[c.doc_ptr[k]:c.doc_ptr[k + 1]]
+        M = cdist(Eq, c.emb[wk].astype(np.float64))
+        assert M.min() * (1 - 1e-5) - 1e-6 <= g32[k] <= M.max() * (1 + 1e-5) + 1e-6
+
+
+# ------------------------------------------------------------------- batched
+
+@pytest.fixture(scope="module")
+def batched():
+    return synth.make_workload("batched", scale_docs=0.02)  # N = 1,000 documents, 64 queries
+
+
+def test_batched_fp32_and_bf16(W, batched):
+    c = corpus_of(W, batched.corpus)
+    g32 = run(W, c, batched.queries, batched.lam, batched.max_iter)
+    g16 = run(W, c, batched.queries, batched.lam, batched.max_iter, cdist="bf16")
+    rng = np.random.default_rng(3)
+    for b in range(batched.queries.B):
+        docs = np.sort(rng.choice(batched.corpus.N, size=12, replace=False))
+        ids, qw = batched.queries.query(b)
+        ref = oracle_support(batched.corpus, ids, qw, batched.lam, batched.max_iter, docs)
+        assert_close(g32[b, docs], ref, TOL32, f"batched fp32 q{b} vr={len(ids)}")
+        assert_close(g16[b, docs], ref, TOL16, f"batched bf16 q{b} vr={len(ids)}")
+
+
+def test_batch_invariance(W, batched):
+    c = corpus_of(W, batched.corpus)
+    full = run(W, c, batched.queries, batched.lam, batched.max_iter)
+    for b in (0, 17, 63):
+        ids, qw = batched.queries.query(b)
+        one = synth.Queries(q_ptr=np.array([0, len(ids)]), ids=ids, weights=qw)
+        alone = run(W, c, one, batched.lam, batched.max_iter)[0]
+        assert np.array_equal(alone, full[b]), f"query {b} differs alone vs in the batch"
+
+
+# ----------------------------------------------------------------- edge cases
+
+def handmade_corpus(rng, V, d, lengths, dup=False):
+    E = (rng.standard_normal((V, d)) / math.sqrt(d)).astype(np.float32)
+    ptr = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    ids = np.concatenate([rng.choice(V, size=n, replace=dup) if n else np.zeros(0, int) for n in lengths])
+    w = rng.integers(1, 5, size=len(ids)).astype(np.float32)
+    return synth.Corpus(V=V, d=d, emb=E, doc_ptr=ptr, word_ids=ids.astype(np.int32), weights=w)
+
+
+def test_single_query_word_closed_form(W):
+    rng = np.random.default_rng(40)
+    c = handmade_corpus(rng, 500, 48, rng.integers(1, 70, size=60))
+    q = synth.Queries(q_ptr=np.array([0, 2]), ids=np.array([7, 7], np.int32), weights=np.array([1, 2], np.float32))
+    got = run(W, corpus_of(W, c), q, 10.0, 15)[0]
+    M = cdist(c.emb[[7]].astype(np.float64), c.emb.astype(np.float64))[0]
+    want = np.array([(c.weights[s:e] / c.weights[s:e].sum() * M[c.word_ids[s:e]]).sum()
+                     for s, e in zip(c.doc_ptr[:-1], c.doc_ptr[1:])])
+    assert_close(got, want, 2e-6, "v_r = 1")
+
+
+def test_empty_zero_weight_and_duplicate_entries(W):
+    rng = np.random.default_rng(41)
+    V, d = 300, 32
+    E = (rng.standard_normal((V, d)) / math.sqrt(d)).astype(np.float32)
+    docs = [([], []), ([5, 9, 5], [1, 2, 3]), ([11, 12], [0, 0]), ([3, 4, 8], [1, 0, 2]), ([250], [4])]
+    ptr = np.concatenate([[0], np.cumsum([len(a) for a, _ in docs])]).astype(np.int64)
+    ids = np.array([i for a, _ in docs for i in a], np.int32)
+    w = np.array([x for _, b in docs for x in b], np.float32)
+    c = synth.Corpus(V=V, d=d, emb=E, doc_ptr=ptr, word_ids=ids, weights=w)
+    q = synth.Queries(q_ptr=np.array([0, 5]), ids=np.array([9, 3, 9, 100, 42], np.int32),
+                      weights=np.array([1, 2, 2, 0, 1], np.float32))
+    got = run(W, corpus_of(W, c), q, 10.0, 15)[0]
+    ref = oracle.wmd_dense_corpus(E, ptr, ids, w, q.ids, q.weights, 10.0, 15)
+    assert np.isnan(got[0]) and np.isnan(got[2])
+    assert_close(got, ref, TOL32, "edge docs")
+
+
+def test_all_length_buckets_and_multiwave_items(W):
+    rng = np.random.default_rng(42)
+    lengths = [1, 2, 15, 16, 17, 33, 64, 65, 127, 128, 200, 256, 257, 511, 700, 1024, 1500, 2048, 3000, 4096]
+    c = handmade_corpus(rng, 6000, 40, lengths)
+    qs = [rng.choice(6000, size=v, replace=False) for v in (3, 21, 70, 150)]
+    q = synth.Queries(q_ptr=np.concatenate([[0], np.cumsum([len(x) for x in qs])]),
+                      ids=np.concatenate(qs).astype(np.int32),
+                      weights=rng.integers(1, 4, size=sum(len(x) for x in qs)).astype(np.float32))
+    got = run(W, corpus_of(W, c), q, 10.0, 15)
+    for b in range(q.B):
+        ids, qw = q.query(b)
+        ref = oracle_support(c, ids, qw, 10.0, 15)
+        assert_close(got[b], ref, TOL32, f"query width {len(ids)}")
+
+
+@pytest.mark.parametrize("vr", [1, 3, 4, 5, 63, 64, 65, 500, 2048])
+def test_query_widths(W, vr):
+    rng = np.random.default_rng(43 + vr)
+    c = handmade_corpus(rng, 4000, 24, rng.integers(1, 60, size=50))
+    ids = rng.choice(4000, size=vr, replace=False).astype(np.int32)
+    q = synth.Queries(q_ptr=np.array([0, vr]), ids=ids, weights=rng.integers(1, 4, size=vr).astype(np.float32))
+    got = run(W, corpus_of(W, c), q, 10.0, 15)[0]
+    ref = oracle_support(c, ids, q.weights, 10.0, 15)
+    assert_close(got, ref, TOL32, f"v_r={vr}")
+
+
+def test_invalid_queries_are_nan_with_codes(W):
+    rng = np.random.default_rng(44)
+    c = handmade_corpus(rng, 300, 16, rng.integers(1, 20, size=10))
+    corpus = corpus_of(W, c)
+    q_ptr = np.array([0, 2, 4, 6, 8])
+    ids = np.array([1, 2, 3, 300, 5, 6, 7, 8], np.int32)
+    w = np.array([1, 1, 1, 1, 1, -1, 0, 0], np.float32)
+    batch = W.QueryBatch.from_arrays(q_ptr, ids, w)
+    with pytest.raises(ValueError):
+        corpus.query(batch, 10.0, 15)
+    out = corpus.query(batch, 10.0, 15, check=False)
+    codes = corpus.query_errors(corpus.last_workspace, 4)
+    assert list(codes) == [0, 1, 2, 3]
+    o = out.cpu().numpy()
+    assert np.all(np.isfinite(o[0])) and np.all(np.isnan(o[1:]))
+
+
+def test_corpus_validation_errors(W):
+    rng = np.random.default_rng(45)
+    c = handmade_corpus(rng, 100, 8, [3, 4])
+    bad_ids = c.word_ids.copy()
+    bad_ids[2] = 100
+    with pytest.raises(W.WMDError):
+        W.Corpus.from_numpy(c.emb, c.doc_ptr, bad_ids, c.weights)
+    bad_w = c.weights.copy()
+    bad_w[0] = -1
+    with pytest.raises(W.WMDError):
+        W.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, bad_w)
+    bad_w[0] = np.nan
+    with pytest.raises(W.WMDError):
+        W.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, bad_w)
+    with pytest.raises(W.WMDError):
+        W.Corpus.from_numpy(c.emb, np.array([0, 4, 3, 7]), c.word_ids, c.weights)
+    long = handmade_corpus(rng, 9000, 8, [4097], dup=True)
+    with pytest.raises(W.WMDError):
+        W.Corpus.from_numpy(long.emb, long.doc_ptr, long.word_ids, long.weights)
