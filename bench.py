@@ -1,0 +1,239 @@
+"""Throughput benchmark of the Sinkhorn WMD hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload single|batched|tiny]
+                    [--cdist fp32|bf16] [--schedule auto|resident|per_iteration|unfused]
+                    [--plain] [--no-cpu-baseline]
+
+A step is one call of the whole path (query selection, cost matrix + K,
+max_iter fused SDDMM-SpMM iterations and the final pass) for the workload's
+query batch against its resident corpus; inputs are in device memory before
+the timed region starts.  The value is target-docs x iterations per second.
+With --plain the batched workload's queries are issued one call each.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "target-docs·iters/s for Sinkhorn WMD (plain vs batched); p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"alu": 157.3, "mfma_fp32": 157.3, "mfma_bf16": 2500.0}
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="single", choices=["tiny", "single", "batched"])
+    ap.add_argument("--cdist", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "resident", "per_iteration", "unfused"])
+    ap.add_argument("--plain", action="store_true", help="batched workload: one call per query")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-compact", action="store_true", help="cost matrix over the full vocabulary")
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2107_06433_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def describe(w, plain: bool) -> str:
+    p = w.info
+    c = w.corpus
+    vr = np.diff(w.queries.q_ptr)
+    vr_txt = f"v_r={int(vr[0])}" if len(vr) == 1 else f"B={len(vr)} v_r={int(vr.min())}-{int(vr.max())} (sum {int(vr.sum())})"
+    mode = " issued one query per call" if plain else ""
+    return (f"{w.name}: V={c.V} d={c.d} N={c.N} docs of {p['n_lo']}-{p['n_hi']} Zipf(1.1) words "
+            f"(nnz={c.nnz}), {vr_txt}, lambda={w.lam:g}, {w.max_iter} iterations{mode}")
+
+
+def cpu_baseline(w, seconds: float):
+    """The FP64 oracle as it stands (dense Algorithm 1 over the full vocabulary),
+    timed on a bounded seeded sample of the workload's documents."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info() if t.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    c = w.corpus
+    rng = np.random.default_rng(7)
+    order = rng.permutation(c.N)
+    ids, qw = w.queries.query(0)
+    block = 64 if c.V >= 50_000 else 256
+    done, t_total = 0, 0.0
+    while t_total < seconds and done < c.N:
+        docs = order[done:done + block]
+        t0 = time.perf_counter()
+        oracle.wmd_dense_corpus(c.emb, c.doc_ptr, c.word_ids, c.weights, ids, qw, w.lam, w.max_iter,
+                                docs=docs, block=block)
+        t_total += time.perf_counter() - t0
+        done += len(docs)
+    dense_rate = done * w.max_iter / t_total
+    # the support-restricted form of the same oracle, same kind of sample
+    t0 = time.perf_counter()
+    ns = 0
+    while time.perf_counter() - t0 < min(5.0, seconds / 3) and ns < c.N:
+        chunk = order[ns:ns + 32]
+        oracle.sinkhorn_wmd_support(c.emb, c.doc_ptr, c.word_ids, c.weights, ids, qw, w.lam, w.max_iter,
+                                    docs=chunk)
+        ns += len(chunk)
+    sup_rate = ns * w.max_iter / (time.perf_counter() - t0)
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {
+        "value": dense_rate, "unit": "docs*iters/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"dense full-vocabulary FP64 Algorithm 1, query 0, {done} seeded random documents "
+                  f"of the same corpus, {t_total:.1f} s",
+        "support_restricted_value": sup_rate,
+        "support_restricted_sample": f"{ns} documents",
+        "cpu_model": cpu, "affinity_cores": len(os.sched_getaffinity(0)),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+              "Documents shard across GPUs with no per-iteration exchange; see DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2107_06433_amd import synth, wmd
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = synth.make_workload(args.workload)
+    c = w.corpus
+    corpus = wmd.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, c.weights, device=dev,
+                                   compact_vocab=not args.no_compact)
+    info = corpus.info()
+    Q = w.queries
+    if args.plain:
+        batches = [wmd.QueryBatch.from_arrays([0, len(Q.query(b)[0])], *Q.query(b), device=dev) for b in range(Q.B)]
+    else:
+        batches = [wmd.QueryBatch.from_arrays(Q.q_ptr, Q.ids, Q.weights, device=dev)]
+    outs = [torch.empty((bt.B, c.N), dtype=torch.float32, device=dev) for bt in batches]
+    wss = [torch.empty(corpus.workspace_bytes(bt, args.schedule), dtype=torch.uint8, device=dev) for bt in batches]
+
+    def step():
+        for bt, o, ws in zip(batches, outs, wss):
+            corpus.query(bt, w.lam, w.max_iter, cdist=args.cdist, schedule=args.schedule, out=o,
+                         workspace=ws, check=False)
+
+    # validity check of the configuration before timing
+    step()
+    torch.cuda.synchronize()
+    for bt, ws in zip(batches, wss):
+        codes = corpus.query_errors(ws, bt.B)
+        assert not codes.any(), codes
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    # timed region: plain, for the value
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    docs_iters = Q.B * c.N * w.max_iter
+    value = docs_iters / (ms / 1e3)
+    print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # the same steps again with HIP events around every kernel launch
+    corpus.set_timing(True)
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    stats = corpus.timing()
+    corpus.set_timing(False)
+    ms_events = (t3 - t2) * 1e3 / args.steps
+    dom = max(stats, key=lambda s: s["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    name = dom["name"]
+    if name.startswith("cdist"):
+        bf16 = ",1," in name
+        gbs = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
+        tfl = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
+        peak_t = PEAK_TFLOPS["mfma_bf16" if bf16 else "mfma_fp32"]
+        if gbs / HBM_PEAK_GBS >= tfl / peak_t:
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            roof = {"bound": "mfma", "achieved": tfl, "peak": peak_t, "unit": "TFLOP/s"}
+    elif args.schedule in ("auto", "resident"):
+        tfl = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": tfl, "peak": PEAK_TFLOPS["alu"], "unit": "TFLOP/s"}
+    else:
+        gbs = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = name
+    roof["avg_launch_us"] = avg_ms * 1e3
+    roof["traffic"] = None
+    try:
+        with open(PMC_FILE) as f:
+            pmc = json.load(f)
+        key = f"{args.workload}|{args.cdist}|{args.schedule}|{'plain' if args.plain else 'batch'}"
+        ent = pmc.get("entries", {}).get(key)
+        if ent and ent.get("kernel") == name and ent.get("source_hash") == source_hash():
+            roof["traffic"] = ent["traffic_bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "docs*iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.cdist == "fp32" else "bf16-gemm+f32",
+        "data": "synthetic (seeded Zipf corpus and N(0,1/d) embeddings; no dataset)",
+        "config": {"workload": describe(w, args.plain), "queries_per_step": Q.B, "docs": c.N,
+                   "max_iter": w.max_iter, "cdist": args.cdist, "schedule": args.schedule,
+                   "compact_vocab": not args.no_compact, "vocab_rows_U": info["U"],
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "kernels": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in s.items()} for s in stats],
+        "ms_per_step_with_events": ms_events,
+        "source_hash": source_hash(),
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

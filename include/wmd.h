@@ -162,6 +162,27 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
  * Copies B int32 into host `codes` and synchronises `stream`. */
 wmd_status wmd_query_errors(const void* workspace, int32_t B, int32_t* codes, void* stream);
 
+/* ------------------------------------------------------- instrumentation */
+
+/* Per-kernel timing for measurement tools.  While enabled on a corpus, every
+ * wmd_query on it brackets each kernel launch with a pair of HIP events on the
+ * caller's stream and records the launch's algorithmic work (flops and bytes
+ * the method must move, not what the hardware counted).  Enabling clears
+ * earlier records; at most 1,000,000 launches are kept. */
+typedef struct {
+  char name[96];      /* kernel and template shape, e.g. "sink_kernel<5,16,0>" */
+  int64_t launches;
+  double total_ms;    /* summed event-to-event duration of those launches      */
+  double flops;       /* summed algorithmic floating-point operations          */
+  double bytes;       /* summed algorithmic bytes read or written              */
+} wmd_kernel_stat;
+
+wmd_status wmd_set_timing(wmd_corpus* c, int32_t enable);
+
+/* Waits for every recorded event, then writes one entry per kernel name
+ * (at most `capacity`) and their number to *count. */
+wmd_status wmd_get_timing(wmd_corpus* c, wmd_kernel_stat* stats, int32_t capacity, int32_t* count);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* wmd_last_error(void);
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,8 +56,61 @@ struct wmd_corpus {
   // documents grouped by length bucket, then the NaN-scoring (empty) ones
   int64_t bucket_off[kNumBuckets + 1] = {};
   int64_t empty_off = 0, empty_count = 0;
+  int64_t bucket_nnz[kNumBuckets] = {};  // entries of the documents in each bucket
   int* docs() const { return at<int>(ws, L.docs); }
+
+  // per-launch timing (wmd_set_timing)
+  struct Rec { std::string name; size_t ev; double flops, bytes; };
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // pool, reused; pairs (start, end)
+  std::vector<Rec> recs;
+
+  // side streams (default priority) that run the independent Sinkhorn launch
+  // groups of a call concurrently, forked from and joined back into the
+  // caller's stream with events
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSide] = {};
+  std::mutex side_mu;  // one call at a time enqueues on the side streams
+
+  ~wmd_corpus() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (int i = 0; i < kSide; ++i) {
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+      if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+  }
 };
+
+namespace {
+
+constexpr size_t kMaxTimedLaunches = 1000000;
+
+// Launches `fn` on stream s; with timing on, brackets it with two events and
+// records its algorithmic work.
+template <class F>
+hipError_t timed_launch(wmd_corpus* c, hipStream_t s, const std::string& name, double flops, double bytes, F&& fn) {
+  if (!c->timing || c->recs.size() >= kMaxTimedLaunches) return fn();
+  const size_t ev = 2 * c->recs.size();
+  while (c->events.size() < ev + 2) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    c->events.push_back(e);
+  }
+  hipError_t err = hipEventRecord(c->events[ev], s);
+  if (err != hipSuccess) return err;
+  err = fn();
+  if (err != hipSuccess) return err;
+  err = hipEventRecord(c->events[ev + 1], s);
+  if (err != hipSuccess) return err;
+  c->recs.push_back({name, ev, flops, bytes});
+  return hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -103,6 +157,11 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
   std::unique_ptr<wmd_corpus> c(new (std::nothrow) wmd_corpus());
   if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "out of host memory");
   WMD_HIP(hipGetDevice(&c->device));
+  for (int i = 0; i < wmd_corpus::kSide; ++i) {
+    WMD_HIP(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+    WMD_HIP(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
+  }
+  WMD_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
   c->V = D.V; c->N = D.N; c->nnz = D.nnz; c->d = D.d; c->dp = padded_dim(D.d);
   c->emb = D.emb; c->doc_ptr = D.doc_ptr;
   c->L = CorpusLayout::make(D.V, D.d, D.N, D.nnz);
@@ -143,6 +202,7 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
     int b = 0;
     while (kBucketCap[b] < len) ++b;
     lists[b].push_back((int)k);
+    c->bucket_nnz[b] += len;
   }
   std::vector<int> flat;
   flat.reserve((size_t)D.N);
@@ -153,7 +213,15 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
   }
   c->bucket_off[kNumBuckets] = c->empty_off;
   c->empty_count = (int64_t)lists[kNumBuckets].size();
+  // per-document records in the same order: first entry (lo, hi), length, id
+  std::vector<int4> rec(flat.size());
+  for (size_t i = 0; i < flat.size(); ++i) {
+    const int k = flat[i];
+    const int64_t b0 = ptr[(size_t)k];
+    rec[i] = make_int4((int)(uint32_t)(b0 & 0xffffffff), (int)(b0 >> 32), (int)(ptr[(size_t)k + 1] - b0), k);
+  }
   WMD_HIP(hipMemcpyAsync(c->docs(), flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, s));
+  WMD_HIP(hipMemcpyAsync(at<int4>(ws, L.drec), rec.data(), sizeof(int4) * rec.size(), hipMemcpyHostToDevice, s));
   WMD_HIP(hipStreamSynchronize(s));
   *out = c.release();
   return WMD_OK;
@@ -262,23 +330,48 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
   sp.r = at<float>(ws, L.r); sp.cinfo = at<int2>(ws, L.cinfo); sp.qn = at<float>(ws, L.qn);
   sp.q32 = at<float>(ws, L.q32); sp.q16 = at<uint16_t>(ws, L.q16);
   sp.want_bf16 = q->cdist == WMD_CDIST_BF16;
-  WMD_HIP(launch_select(sp, s));
+  const double T = (double)q->q_ptr_host[q->B];  // raw query entries = sum of v_r
+  const double esz = q->cdist == WMD_CDIST_BF16 ? 2.0 : 4.0;
+  WMD_HIP(timed_launch(c, s, "select_kernel", 0.0, T * 8.0 + T * c->d * 4.0 + (double)plan.C * c->dp * (4.0 + esz),
+                       [&] { return launch_select(sp, s); }));
 
   // a2 + a3: cost matrix and K for every query word in one GEMM
   float* kt = at<float>(ws, L.kt);
-  float* kmt = at<float>(ws, L.kmt);
   if (c->U > 0) {
     CdistParams cp{};
     cp.e32 = at<float>(c->ws, CL.e32); cp.e16 = at<uint16_t>(c->ws, CL.e16); cp.en = at<float>(c->ws, CL.en);
     cp.used = at<int>(c->ws, CL.used); cp.U = c->U;
     cp.q32 = sp.q32; cp.q16 = sp.q16; cp.qn = sp.qn; cp.qid = sp.qid; cp.cinfo = sp.cinfo;
-    cp.C = plan.C; cp.dp = c->dp; cp.lam = q->lambda; cp.kt = kt; cp.kmt = kmt;
-    WMD_HIP(launch_cdist(cp, q->cdist == WMD_CDIST_BF16, s));
+    cp.C = plan.C; cp.dp = c->dp; cp.lam = q->lambda; cp.kt = kt;
+    // algorithmic work: 2 U d flops per query word; read the U x d vocabulary
+    // rows and the query rows once, write K^T
+    const double U = (double)c->U;
+    const double flops = 2.0 * U * T * c->d;
+    const double bytes = U * c->d * esz + T * c->d * esz + U * 4.0 + U * (double)plan.C * 4.0;
+    // the tile shape is picked inside the launch; its name is filled in afterwards
+    const char* name = "cdist_kernel";
+    const size_t nrec = c->recs.size();
+    WMD_HIP(timed_launch(c, s, "", flops, bytes, [&] { return launch_cdist(cp, q->cdist == WMD_CDIST_BF16, s, &name); }));
+    if (c->recs.size() > nrec) c->recs.back().name = name;
   }
 
-  // a4-a6: Sinkhorn iterations and the final pass, per query and length bucket
+  // a4-a6: Sinkhorn iterations and the final pass, per query and length bucket.
+  // Each (query, bucket) group is independent of the others; with more than
+  // one group they are spread over the side streams.
   float* ubuf = at<float>(ws, L.u);
   float* wbuf = at<float>(ws, L.w);
+  int groups = 0;
+  for (int b = 0; b < q->B; ++b)
+    for (int bk = 0; bk < kNumBuckets; ++bk) groups += c->bucket_off[bk + 1] > c->bucket_off[bk];
+  const bool fork = groups > 3;
+  std::unique_lock<std::mutex> side_lock(c->side_mu, std::defer_lock);
+  bool used_side[wmd_corpus::kSide] = {};
+  if (fork) {
+    side_lock.lock();
+    WMD_HIP(hipEventRecord(c->fork_ev, s));
+    for (int i = 0; i < wmd_corpus::kSide; ++i) WMD_HIP(hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
+  }
+  int group = 0;
   for (int b = 0; b < q->B; ++b) {
     const int64_t col0 = plan.col0[(size_t)b];
     const int S = (int)plan.S[(size_t)b];
@@ -287,47 +380,111 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
       const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
       if (nd == 0) continue;
       SinkConfig cfg{};
-      if (!choose_sink_config(S, kBucketCap[bk], &cfg))
+      if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &cfg))
         return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
                                                " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
       SinkParams p{};
       p.kt = kt + (size_t)col0 * (size_t)c->U;
-      p.kmt = kmt + (size_t)col0 * (size_t)c->U;
       p.r = sp.r + col0;
       p.vr = sp.vr + b;
-      p.doc_ptr = c->doc_ptr; p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);
-      p.docs = c->docs() + c->bucket_off[bk];
+      p.drec = at<int4>(c->ws, CL.drec) + c->bucket_off[bk];
+      p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);
       p.ndocs = (int)nd;
       p.S = S;
+      p.inv_lam = 1.0f / q->lambda;
       p.out = orow;
       p.u = ubuf + (size_t)col0 * (size_t)c->N;
       p.w = wbuf + (size_t)b * (size_t)c->nnz;
       const int grid = sink_grid(cfg, (int)nd);
+      const int si = group++ % wmd_corpus::kSide;
+      hipStream_t gs = fork ? c->side[si] : s;
+      used_side[si] = used_side[si] || fork;
+      // algorithmic work per document and iteration (n_k entries, v_r query words):
+      // 4 v_r n_k + n_k + 2 v_r flops; 8 n_k + 4 v_r n_k + 8 v_r bytes when u and the
+      // K^T rows travel through memory every pass.  The final pass does
+      // 4 v_r n_k + 2 n_k flops.
+      const double vrq = (double)(q->q_ptr_host[b + 1] - q->q_ptr_host[b]);
+      const double nzb = (double)c->bucket_nnz[bk], ndd = (double)nd;
+      const double it_flops = 4.0 * vrq * nzb + nzb + 2.0 * vrq * ndd;
+      const double it_bytes = 8.0 * nzb + 4.0 * vrq * nzb + 8.0 * vrq * ndd;
+      const double fin_flops = 4.0 * vrq * nzb + 2.0 * nzb;
+      const std::string name = cfg.stream ? std::string("sink_stream_kernel")
+                                          : "sink_kernel<" + std::to_string(cfg.tc) + "," + std::to_string(cfg.tr) +
+                                                "," + std::to_string(cfg.lg_cg) + "," +
+                                                (cfg.multiwave ? "true>x" + std::to_string(cfg.nwaves) : "false>");
+      auto go = [&](const SinkParams& a, double fl, double by) {
+        return timed_launch(c, gs, name, fl, by, [&] { return launch_sink(a, cfg, grid, gs); });
+      };
       if (schedule == WMD_SCHEDULE_RESIDENT) {
         p.iters = q->max_iter; p.do_final = 1;
-        WMD_HIP(launch_sink(p, cfg, grid, s));
+        // resident: the entries, the document records and the K^T rows are read once
+        WMD_HIP(go(p, q->max_iter * it_flops + fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 20.0 * ndd));
       } else {
         for (int it = 0; it < q->max_iter; ++it) {
           if (schedule == WMD_SCHEDULE_PER_ITERATION) {
             SinkParams a = p;
             a.iters = 1; a.load_u = it > 0; a.store_u = 1;
-            WMD_HIP(launch_sink(a, cfg, grid, s));
+            WMD_HIP(go(a, it_flops, it_bytes));
           } else {
             SinkParams a = p;  // SDDMM: w_j = c_j / (K_j . u)
             a.iters = 1; a.load_u = it > 0; a.store_w = 1;
-            WMD_HIP(launch_sink(a, cfg, grid, s));
+            WMD_HIP(go(a, 2.0 * vrq * nzb + nzb, 12.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd));
             SinkParams m = p;  // SpMM: acc = K w, u = r / acc
             m.iters = 1; m.load_w = 1; m.store_u = 1;
-            WMD_HIP(launch_sink(m, cfg, grid, s));
+            WMD_HIP(go(m, 2.0 * vrq * nzb + 2.0 * vrq * ndd, 8.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd));
           }
         }
         SinkParams f = p;
         f.iters = 0; f.load_u = q->max_iter > 0; f.do_final = 1;
-        WMD_HIP(launch_sink(f, cfg, grid, s));
+        WMD_HIP(go(f, fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd + 20.0 * ndd));
       }
     }
-    if (c->empty_count > 0) WMD_HIP(launch_nan_docs(c->docs() + c->empty_off, c->empty_count, orow, s));
+    if (c->empty_count > 0)
+      WMD_HIP(timed_launch(c, s, "nan_docs_kernel", 0.0, 8.0 * c->empty_count,
+                           [&] { return launch_nan_docs(c->docs() + c->empty_off, c->empty_count, orow, s); }));
   }
+  if (fork)
+    for (int i = 0; i < wmd_corpus::kSide; ++i) {
+      if (!used_side[i]) continue;
+      WMD_HIP(hipEventRecord(c->join_ev[i], c->side[i]));
+      WMD_HIP(hipStreamWaitEvent(s, c->join_ev[i], 0));
+    }
+  return WMD_OK;
+}
+
+wmd_status wmd_set_timing(wmd_corpus* c, int32_t enable) {
+  g_err.clear();
+  if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
+  c->timing = enable != 0;
+  c->recs.clear();
+  return WMD_OK;
+}
+
+wmd_status wmd_get_timing(wmd_corpus* c, wmd_kernel_stat* stats, int32_t capacity, int32_t* count) {
+  g_err.clear();
+  if (!c || !count || (capacity > 0 && !stats)) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::vector<std::string> names;
+  std::vector<wmd_kernel_stat> acc;
+  for (const auto& r : c->recs) {
+    WMD_HIP(hipEventSynchronize(c->events[r.ev + 1]));
+    float ms = 0.f;
+    WMD_HIP(hipEventElapsedTime(&ms, c->events[r.ev], c->events[r.ev + 1]));
+    size_t i = 0;
+    while (i < names.size() && names[i] != r.name) ++i;
+    if (i == names.size()) {
+      names.push_back(r.name);
+      wmd_kernel_stat z{};
+      std::snprintf(z.name, sizeof(z.name), "%s", r.name.c_str());
+      acc.push_back(z);
+    }
+    acc[i].launches += 1;
+    acc[i].total_ms += ms;
+    acc[i].flops += r.flops;
+    acc[i].bytes += r.bytes;
+  }
+  const int32_t n = (int32_t)acc.size();
+  for (int32_t i = 0; i < n && i < capacity; ++i) stats[i] = acc[(size_t)i];
+  *count = n;
   return WMD_OK;
 }
 

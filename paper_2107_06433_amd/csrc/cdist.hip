@@ -6,8 +6,9 @@
 // widths).  The epilogue turns each G[t][n] into
 //     M = sqrt(max(0, |e_t|^2 + |q_n|^2 - 2 G)),  M = 0 when word t IS query word n,
 //     K = exp(-lambda M),
-// and stores K and K.*M transposed per query: row t of query b is S_b
-// contiguous floats, the row the fused SDDMM-SpMM gathers for every nonzero.
+// and stores K transposed per query: row t of query b is S_b contiguous floats,
+// the row the fused SDDMM-SpMM gathers for every nonzero.  K.*M is not stored:
+// the final pass recovers M = -ln(K) / lambda from the K values it holds.
 //
 // FP32 inputs use v_mfma_f32_16x16x4_f32; BF16 inputs use gfx950's
 // v_mfma_f32_16x16x32_bf16; accumulation is float32 in both.  Both operands
@@ -157,22 +158,19 @@ __global__ void __launch_bounds__(256) cdist_kernel(CdistParams p) {
     const float qn = p.qn[n];
     const int2 ci = p.cinfo[n];
     float* kt = p.kt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
-    float* kmt = p.kmt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
 #pragma unroll
     for (int a = 0; a < T::FM; ++a)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t m = m0 + wm * T::TM + a * 16 + 4 * (lane >> 4) + i;
         if (m >= p.U) continue;
-        float kv = 0.f, kmv = 0.f;
+        float kv = 0.f;
         if (q >= 0) {
           const float m2 = p.en[m] + qn - 2.f * acc[a][b][i];
           const float dist = p.used[m] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
           kv = expf(-p.lam * dist);
-          kmv = kv * dist;
         }
         kt[(size_t)m * ci.y] = kv;
-        kmt[(size_t)m * ci.y] = kmv;
       }
   }
 }
@@ -185,12 +183,127 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// Few query columns (C <= 32): the GEMM is a stream over the U x dp vocabulary
+// rows.  Each wave owns 16 rows and reads them straight from memory into the
+// MFMA operand registers -- for every 16 (f32) or 32 (bf16) k values, the four
+// lane quads of a row read one contiguous 64-byte piece -- with a chunk of
+// loads kept in flight ahead of the MFMAs.  Q (at most 32 rows) is staged once
+// per block in LDS.
+template <int NT, bool BF16>
+__global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
+  constexpr int ESZ = BF16 ? 2 : 4;
+  constexpr int KS = BF16 ? 32 : 16;        // k values per 16-byte-per-lane load step
+  constexpr int CH = 8;                     // load steps per chunk
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int dp = p.dp;
+  const size_t row_bytes = (size_t)dp * ESZ;
+  const int ldq = dp * ESZ + 16;            // LDS row pitch in bytes (one 16-byte pad)
+  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int64_t myrow = m0 + (lane & 15);
+  const bool row_ok = myrow < p.U;
+  const unsigned char* Ag = (BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32) +
+                            (size_t)(row_ok ? myrow : 0) * row_bytes + 16 * (lane >> 4);
+  const int nsteps = dp / KS;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 buf[CH];
+  auto load = [&](int s0) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      buf[i] = (row_ok && s0 + i < nsteps) ? *(const uint4*)(Ag + (size_t)(s0 + i) * 64) : make_uint4(0, 0, 0, 0);
+  };
+  load(0);  // the first vocabulary loads are in flight while Q is staged
+  // stage Q: NT*16 rows (zero beyond C)
+  const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
+  const int vpr = dp * ESZ / 16;
+  for (int i = tid; i < NT * 16 * vpr; i += 256) {
+    const int row = i / vpr, v = i % vpr;
+    uint4 x = make_uint4(0, 0, 0, 0);
+    if (row < p.C) x = *(const uint4*)(Qg + (size_t)row * row_bytes + 16 * v);
+    *(uint4*)(smem + row * ldq + 16 * v) = x;
+  }
+  __syncthreads();
+  for (int s0 = 0; s0 < nsteps; s0 += CH) {
+    uint4 cur[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) cur[i] = buf[i];
+    if (s0 + CH < nsteps) load(s0 + CH);
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      if (s0 + i >= nsteps) break;
+      const int kb = (s0 + i) * 64 + 16 * (lane >> 4);  // byte offset of this lane's k run
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const uint4 q = *(const uint4*)(smem + (t * 16 + (lane & 15)) * ldq + kb);
+        if constexpr (BF16) {
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[i]),
+                                                          __builtin_bit_cast(bf16x8, q), acc[t], 0, 0, 0);
+        } else {
+          const f32x4 a = __builtin_bit_cast(f32x4, cur[i]);
+          const f32x4 b = __builtin_bit_cast(f32x4, q);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // epilogue: register i of lane l holds row 4*(l/16)+i, column l%16 of each tile
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int64_t n = t * 16 + (lane & 15);
+    if (n >= p.C) continue;
+    const int q = p.qid[n];
+    const float qn = p.qn[n];
+    const int2 ci = p.cinfo[n];
+    float* kt = p.kt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t m = m0 + 4 * (lane >> 4) + i;
+      if (m >= p.U) continue;
+      float kv = 0.f;
+      if (q >= 0) {
+        const float m2 = p.en[m] + qn - 2.f * acc[t][i];
+        const float dist = p.used[m] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
+        kv = expf(-p.lam * dist);
+      }
+      kt[(size_t)m * ci.y] = kv;
+    }
+  }
+}
+
+template <int NT, bool BF16>
+hipError_t run_skinny(const CdistParams& p, hipStream_t s) {
+  const size_t lds = (size_t)NT * 16 * (p.dp * (BF16 ? 2 : 4) + 16);
+  const unsigned grid = (unsigned)((p.U + 63) / 64);
+  cdist_skinny_kernel<NT, BF16><<<grid, 256, lds, s>>>(p);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s) {
+hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name) {
   if (p.U <= 0 || p.C <= 0) return hipSuccess;
-  if (p.C <= 32) return bf16 ? run<64, 32, 4, true, 64>(p, s) : run<64, 32, 4, false, 32>(p, s);
-  if (p.C <= 64) return bf16 ? run<128, 64, 2, true, 64>(p, s) : run<128, 64, 2, false, 32>(p, s);
+  const size_t skinny_lds = (size_t)32 * (p.dp * (bf16 ? 2 : 4) + 16);
+  if (p.C <= 16 && skinny_lds / 2 <= 65536) {
+    *name = bf16 ? "cdist_skinny_kernel<1,1>" : "cdist_skinny_kernel<1,0>";
+    return bf16 ? run_skinny<1, true>(p, s) : run_skinny<1, false>(p, s);
+  }
+  if (p.C <= 32 && skinny_lds <= 65536) {
+    *name = bf16 ? "cdist_skinny_kernel<2,1>" : "cdist_skinny_kernel<2,0>";
+    return bf16 ? run_skinny<2, true>(p, s) : run_skinny<2, false>(p, s);
+  }
+  if (p.C <= 32) {
+    *name = bf16 ? "cdist_kernel<64,32,4,1,64>" : "cdist_kernel<64,32,4,0,32>";
+    return bf16 ? run<64, 32, 4, true, 64>(p, s) : run<64, 32, 4, false, 32>(p, s);
+  }
+  if (p.C <= 64) {
+    *name = bf16 ? "cdist_kernel<128,64,2,1,64>" : "cdist_kernel<128,64,2,0,32>";
+    return bf16 ? run<128, 64, 2, true, 64>(p, s) : run<128, 64, 2, false, 32>(p, s);
+  }
+  *name = bf16 ? "cdist_kernel<128,128,2,1,32>" : "cdist_kernel<128,128,2,0,16>";
   return bf16 ? run<128, 128, 2, true, 32>(p, s) : run<128, 128, 2, false, 16>(p, s);
 }
 

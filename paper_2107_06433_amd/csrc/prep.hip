@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
   __shared__ float s_w[kMaxQueryLen];
   __shared__ double s_m[kMaxQueryLen];
   __shared__ int s_pos[kMaxQueryLen];
+  __shared__ int s_slot[kMaxQueryLen];
   __shared__ long long s_red[256];
   __shared__ double s_dred[256];
   __shared__ int s_err;
@@ -162,33 +163,40 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
     p.err[b] = err & 1 ? 1 : err & 2 ? 2 : err & 4 ? 4 : err & 8 ? 3 : 0;
     p.vr[b] = vr;
   }
-  for (int s = t; s < S; s += 256) {
-    p.qid[col0 + s] = -1;
-    p.r[col0 + s] = 0.f;
-    p.cinfo[col0 + s] = make_int2((int)col0, S);
-  }
+  // slot -> vocabulary id, kept in LDS for the row copies below
+  for (int s = t; s < S; s += 256) s_slot[s] = -1;
   __syncthreads();
   if (vr > 0)
     for (int i = t; i < nn; i += 256)
-      if (s_pos[i] >= 0) {
-        p.qid[col0 + s_pos[i]] = s_id[i];
-        p.r[col0 + s_pos[i]] = (float)(s_m[i] / tot);
-      }
+      if (s_pos[i] >= 0) s_slot[s_pos[i]] = i;
   __syncthreads();
-  // embedding rows of the slots (one wave per slot)
-  const int lane = t & 63;
-  for (int s = t >> 6; s < S; s += 4) {
-    const int q = p.qid[col0 + s];
+  for (int s = t; s < S; s += 256) {
+    const int i = s_slot[s];
+    p.qid[col0 + s] = i >= 0 ? s_id[i] : -1;
+    p.r[col0 + s] = i >= 0 ? (float)(s_m[i] / tot) : 0.f;
+    p.cinfo[col0 + s] = make_int2((int)col0, S);
+  }
+  // embedding rows of the slots and their squared norms: 8 lanes per slot,
+  // 32 slots per pass, every row load of a pass in flight together; the norm
+  // is a double sum in a fixed order (strided partials, then a 3-step tree)
+  const int g = t >> 3, lane8 = t & 7;
+  for (int s0 = 0; s0 < S; s0 += 32) {
+    const int s = s0 + g;
+    const int i = s < S ? s_slot[s] : -1;
+    const int q = i >= 0 ? s_id[i] : -1;
     const float* src = p.emb + (size_t)(q < 0 ? 0 : q) * p.d;
     double nrm = 0.0;
-    for (int k = lane; k < p.dp; k += 64) {
-      const float x = (q >= 0 && k < p.d) ? src[k] : 0.f;
-      p.q32[(size_t)(col0 + s) * p.dp + k] = x;
-      if (p.want_bf16) p.q16[(size_t)(col0 + s) * p.dp + k] = f32_to_bf16(x);
-      nrm += (double)x * (double)x;
-    }
-    for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off);
-    if (lane == 0) p.qn[col0 + s] = (float)nrm;
+    if (s < S)
+      for (int k = lane8; k < p.dp; k += 8) {
+        const float x = (q >= 0 && k < p.d) ? src[k] : 0.f;
+        p.q32[(size_t)(col0 + s) * p.dp + k] = x;
+        if (p.want_bf16) p.q16[(size_t)(col0 + s) * p.dp + k] = f32_to_bf16(x);
+        nrm += (double)x * (double)x;
+      }
+    nrm += __shfl_xor(nrm, 1, 8);
+    nrm += __shfl_xor(nrm, 2, 8);
+    nrm += __shfl_xor(nrm, 4, 8);
+    if (s < S && lane8 == 0) p.qn[col0 + s] = (float)nrm;
   }
 }
 

@@ -1,0 +1,324 @@
+// Fused SDDMM-SpMM Sinkhorn-Knopp iterations and the final distance pass
+// (Algorithm 1 loop and last line; Section III-C, SDDMM_SpMM type 1 and 2).
+//
+// Work item = one (query, target document) pair.  Documents are independent
+// through the whole loop: x_k depends only on u_k, the K^T rows of document
+// k's words and c_k.  Each item therefore owns private lanes, the doc-major
+// layout needs no atomics (the paper's row split does), and every sum has a
+// fixed order, so results are deterministic.
+//
+// Lane grid of an item: CG = 2^LG_CG column lanes x RS row lanes, one wave
+// (64 lanes) or `nwaves` waves of one block (MW).  Column lane cg holds the
+// query words cg, cg+CG, ... (TC of them); row lane rs holds the document
+// words rs, rs+RS, ... (TR of them).  Each lane keeps its TR x TC block of the
+// gathered K^T rows in registers, so every iteration reads each element
+// twice -- for the dot product s_j = K_j . u (SDDMM) and for the update
+// acc += K_j w_j (SpMM) -- the paper's fusion, with no sparse intermediate:
+//
+//   s_j   = sum over the column lanes of the lane-local dot products
+//   w_j   = c_jk / s_j                              (only where c_jk > 0)
+//   acc_i = sum over the row lanes of K_ji w_j
+//   u_i   = r_i / acc_i                             (x = acc / r, u = 1/x)
+//
+// The final pass computes s_j and t_j = (K.*M)_j . u and
+// d_k = sum_j c_jk t_j / s_j = sum(u .* ((K.*M) v)) with v_j = c_jk / s_j,
+// recovering each M entry from the K entry it already holds.
+// The lane geometry is compile-time so every cross-lane sum is a fixed
+// sequence of DPP / permlane steps the compiler can interleave across rows.
+#pragma once
+
+#include "lanes.h"
+#include "wmd_internal.h"
+
+namespace wmd {
+
+// Sum over lane bits [0, NB) of every element of x, step by step across the
+// array so independent DPP chains interleave.  Lower bits first: the mirror
+// patterns flip several bits at once and are only sums once the lower bits
+// hold equal values.
+template <int NB, int N>
+__device__ __forceinline__ void sum_low(float (&x)[N]) {
+  if constexpr (NB > 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppXor1>(x[i]);
+  }
+  if constexpr (NB > 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppXor2>(x[i]);
+  }
+  if constexpr (NB > 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppHalfMirror>(x[i]);
+  }
+  if constexpr (NB > 3) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppMirror>(x[i]);
+  }
+  if constexpr (NB > 4) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = add_xor16(x[i]);
+  }
+  if constexpr (NB > 5) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = add_xor32(x[i]);
+  }
+}
+
+// Sum over lane bits [LO, 6) of a wave; bits below LO address different values.
+// Bits 2 and 3 together are row_ror:8 then row_ror:4 (a clean 4-lane sum only
+// when both are summed, which holds since the range always ends at bit 6).
+template <int LO, int N>
+__device__ __forceinline__ void sum_high(float (&x)[N]) {
+  if constexpr (LO <= 3) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppRor8>(x[i]);
+  }
+  if constexpr (LO <= 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppRor4>(x[i]);
+  }
+  if constexpr (LO <= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppXor2>(x[i]);
+  }
+  if constexpr (LO <= 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] += dpp<kDppXor1>(x[i]);
+  }
+  if constexpr (LO <= 4) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = add_xor16(x[i]);
+  }
+  if constexpr (LO <= 5) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = add_xor32(x[i]);
+  }
+}
+
+// The cost M of a kernel entry K = exp(-lambda M), recovered as -ln(K) / lambda.
+// K = 1 (the same word) gives exactly 0; an entry at or below the smallest
+// normal float contributes K * M ~ 0 and is dropped.
+__device__ __forceinline__ float cost_from_gibbs(float k, float inv_lam) {
+  return k > 1.17549435e-38f ? -__logf(k) * inv_lam : 0.f;
+}
+
+__device__ __forceinline__ int64_t rec_begin(const int4& r) {
+  return (int64_t)(uint32_t)r.x | ((int64_t)r.y << 32);
+}
+
+template <int TC, int TR, int LG_CG, int MAXW>
+__global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParams p) {
+  constexpr bool MW = MAXW > 1;                   // an item spans several waves of one block
+  constexpr int CG = 1 << LG_CG;
+  constexpr int RSW = 64 >> LG_CG;                // row lanes per wave
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = MW ? (int)(blockDim.x >> 6) : 1;
+  const int cg = lane & (CG - 1);
+  const int rs = (MW ? wave * RSW : 0) + (lane >> LG_CG);
+  const int RS = nwaves * RSW;
+  const int items = MW ? 1 : (int)(blockDim.x >> 6);
+  const int slot = MW ? 0 : wave;
+  constexpr int cw_stride = CG * TC;              // LDS floats per wave and buffer
+  const int S = p.S;
+  const int vr = *p.vr;
+
+  for (int base = blockIdx.x * items; base < p.ndocs; base += gridDim.x * items) {
+    const int item = base + slot;
+    const bool active = item < p.ndocs;
+    const int4 rec = active ? p.drec[item] : make_int4(0, 0, 0, 0);
+    const int64_t beg = rec_begin(rec);
+    const int n = rec.z, k = rec.w;
+
+    // ---- gather this lane's words of document k and their K^T entries.  A
+    // row slot with no word (or a zero weight) is padding: its K row is zero
+    // and column lane 0 seeds its dot product with 1, so w = 0 * rcp(1) = 0.
+    int wid[TR];
+    float cw[TR], rpad[TR];
+    float K[TR][TC];
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      const int j = rs + RS * t;
+      const int id = j < n ? p.wl[beg + j] : -1;
+      const float c = j < n ? p.wn[beg + j] : 0.f;
+      wid[t] = c > 0.f ? id : -1;
+      cw[t] = c > 0.f ? c : 0.f;
+      rpad[t] = (wid[t] < 0 && cg == 0) ? 1.f : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      const float* row = p.kt + (size_t)(wid[t] < 0 ? 0 : wid[t]) * S;
+#pragma unroll
+      for (int e = 0; e < TC; ++e) {
+        const int col = cg + CG * e;
+        const float v = row[col < S ? col : S - 1];  // clamped: never reads past the row
+        K[t][e] = (wid[t] >= 0 && col < S) ? v : 0.f;
+      }
+    }
+    // Column slots past the query's words are padding too: K is zero there
+    // and row lane 0 seeds their sum with 1, so u = 0 * rcp(1) = 0.
+    float rv[TC], u[TC], cpad[TC];
+#pragma unroll
+    for (int e = 0; e < TC; ++e) {
+      const int col = cg + CG * e;
+      rv[e] = col < S ? p.r[col] : 0.f;
+      cpad[e] = (rv[e] > 0.f || rs != 0) ? 0.f : 1.f;
+      if (p.load_u)
+        u[e] = (active && col < S) ? p.u[(size_t)k * S + col] : 0.f;
+      else
+        u[e] = rv[e] > 0.f ? (float)vr : 0.f;  // x = 1/v_r
+    }
+    float wv[TR];
+    if (p.load_w) {
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int j = rs + RS * t;
+        wv[t] = (j < n && wid[t] >= 0) ? p.w[beg + j] : 0.f;
+      }
+    }
+
+    // ---- Sinkhorn-Knopp iterations
+    for (int it = 0; it < p.iters; ++it) {
+      if (!p.load_w) {
+        float s[TR];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+          float a = rpad[t];
+#pragma unroll
+          for (int e = 0; e < TC; ++e) a = fmaf(K[t][e], u[e], a);
+          s[t] = a;
+        }
+        sum_low<LG_CG>(s);
+#pragma unroll
+        for (int t = 0; t < TR; ++t) wv[t] = fast_div(cw[t], s[t]);
+        if (p.store_w) {
+          if (cg == 0 && active) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+              const int j = rs + RS * t;
+              if (j < n) p.w[beg + j] = wv[t];
+            }
+          }
+          continue;
+        }
+      }
+      float acc[TC];
+#pragma unroll
+      for (int e = 0; e < TC; ++e) {
+        float a = cpad[e];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) a = fmaf(K[t][e], wv[t], a);
+        acc[e] = a;
+      }
+      sum_high<LG_CG>(acc);
+      if constexpr (MW) {
+        // cross-wave sum in two phases: every wave posts its column partials,
+        // one thread per column adds them in wave order, every lane reads back
+        // its columns.  Both arrays alternate by iteration parity, so two
+        // barriers per iteration suffice.
+        float* part = lds + (it & 1) * nwaves * cw_stride;
+        float* tot = lds + 2 * nwaves * cw_stride + (it & 1) * cw_stride;
+        if (lane < CG) {
+#pragma unroll
+          for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < cw_stride; c += blockDim.x) {
+          float a = 0.f;
+          for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + c];
+          tot[c] = a;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < TC; ++e) acc[e] = tot[cg + CG * e];
+      }
+#pragma unroll
+      for (int e = 0; e < TC; ++e) u[e] = fast_div(rv[e], acc[e]);
+    }
+
+    if (p.store_u && rs == 0 && active) {
+#pragma unroll
+      for (int e = 0; e < TC; ++e) {
+        const int col = cg + CG * e;
+        if (col < S) p.u[(size_t)k * S + col] = u[e];
+      }
+    }
+
+    // ---- final pass: d_k = sum_j c_jk ((K.*M)_j . u) / (K_j . u), with the
+    // costs recovered from the K entries held in registers
+    if (p.do_final) {
+      float sa[TR], sb[TR];
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        float a = rpad[t], b = 0.f;
+#pragma unroll
+        for (int e = 0; e < TC; ++e) {
+          const float ku = K[t][e] * u[e];
+          a += ku;
+          b = fmaf(ku, cost_from_gibbs(K[t][e], p.inv_lam), b);
+        }
+        sa[t] = a;
+        sb[t] = b;
+      }
+      sum_low<LG_CG>(sa);
+      sum_low<LG_CG>(sb);
+      float part[1] = {0.f};
+#pragma unroll
+      for (int t = 0; t < TR; ++t) part[0] = fmaf(cw[t], fast_div(sb[t], sa[t]), part[0]);
+      part[0] = cg == 0 ? part[0] : 0.f;
+      sum_low<6>(part);
+      float tot = part[0];
+      if constexpr (MW) {
+        __syncthreads();  // the last iteration's totals may still be read
+        if (lane == 0) lds[wave] = tot;
+        __syncthreads();
+        float a = 0.f;
+        for (int w = 0; w < nwaves; ++w) a += lds[w];
+        tot = a;
+        __syncthreads();
+      }
+      if (lane == 0 && (MW ? wave == 0 : true) && active) p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
+    }
+  }
+}
+
+using SinkFn = void (*)(SinkParams);
+
+struct SinkEntry {
+  int tc, tr, lg_cg;
+  int maxw;   // 1: one wave per item; 4 or 16: waves per block at most
+  SinkFn fn;
+};
+
+// Register budget per lane of the K^T block: up to 128 cells with at most 4
+// waves per block (up to 512 VGPRs per lane), up to 64 cells in 16-wave
+// blocks (128 VGPRs per lane).
+template <int TC, int TR, int MAXW>
+constexpr bool kSinkFits = TC * TR <= (MAXW == 16 ? 64 : 128);
+
+#define WMD_SINK_SW_TR(X, TC, LG) X(TC, 1, LG, 1) X(TC, 2, LG, 1) X(TC, 4, LG, 1) X(TC, 8, LG, 1) X(TC, 16, LG, 1)
+#define WMD_SINK_MW_TR(X, TC, LG) X(TC, 8, LG, 4) X(TC, 16, LG, 4) X(TC, 4, LG, 16) X(TC, 8, LG, 16)
+#define WMD_SINK_TC(X, TC, LG) WMD_SINK_SW_TR(X, TC, LG) WMD_SINK_MW_TR(X, TC, LG)
+
+template <int TC, int TR, int LG_CG, int MAXW, bool OK = kSinkFits<TC, TR, MAXW>>
+struct SinkPick {
+  static SinkEntry get() { return SinkEntry{TC, TR, LG_CG, MAXW, nullptr}; }
+};
+template <int TC, int TR, int LG_CG, int MAXW>
+struct SinkPick<TC, TR, LG_CG, MAXW, true> {
+  static SinkEntry get() { return SinkEntry{TC, TR, LG_CG, MAXW, (SinkFn)sink_kernel<TC, TR, LG_CG, MAXW>}; }
+};
+
+#define WMD_SINK_ENTRY(TC, TR, LG, MAXW) SinkPick<TC, TR, LG, MAXW>::get(),
+
+// Tables of the instantiated shapes, one per translation unit (column-lane width).
+const SinkEntry* sink_table_cg0(int* n);
+const SinkEntry* sink_table_cg1(int* n);
+const SinkEntry* sink_table_cg2(int* n);
+const SinkEntry* sink_table_cg3(int* n);
+const SinkEntry* sink_table_cg4(int* n);
+const SinkEntry* sink_table_cg5(int* n);
+const SinkEntry* sink_table_cg6(int* n);
+
+}  // namespace wmd

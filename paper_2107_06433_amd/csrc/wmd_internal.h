@@ -22,7 +22,7 @@ inline int padded_dim(int d) { return (d + 63) / 64 * 64; }
 
 // Corpus workspace: derived arrays built once by wmd_create_corpus.
 struct CorpusLayout {
-  size_t err, wn, wl, map, used, dpos, docs, en, e32, e16, total;
+  size_t err, wn, wl, map, used, dpos, docs, drec, en, e32, e16, total;
   static CorpusLayout make(int64_t V, int d, int64_t N, int64_t nnz) {
     CorpusLayout L{};
     const int dp = padded_dim(d);
@@ -35,6 +35,7 @@ struct CorpusLayout {
     L.used = take(sizeof(int) * (size_t)V);             // compacted row -> vocab id
     L.dpos = take(sizeof(int) * (size_t)N);             // doc has positive mass
     L.docs = take(sizeof(int) * (size_t)N);             // docs grouped by length bucket
+    L.drec = take(sizeof(int4) * (size_t)N);            // (first entry lo/hi, length, id) per doc, same order
     L.en = take(sizeof(float) * (size_t)V);             // |e|^2 of compacted rows
     L.e32 = take(sizeof(float) * (size_t)V * dp);       // compacted embeddings, f32
     L.e16 = take(sizeof(uint16_t) * (size_t)V * dp);    // same, bf16
@@ -47,7 +48,7 @@ struct CorpusLayout {
 // codes sit at offset 0 so that wmd_query_errors() can find them from the
 // workspace pointer alone.
 struct QueryLayout {
-  size_t err, vr, qid, r, cinfo, qn, q32, q16, kt, kmt, u, w, total;
+  size_t err, vr, qid, r, cinfo, qn, q32, q16, kt, u, w, total;
   static QueryLayout make(int B, int64_t C, int64_t U, int dp, int64_t N, int64_t nnz,
                           bool need_u, bool need_w) {
     QueryLayout L{};
@@ -62,7 +63,6 @@ struct QueryLayout {
     L.q32 = take(sizeof(float) * (size_t)C * dp);
     L.q16 = take(sizeof(uint16_t) * (size_t)C * dp);
     L.kt = take(sizeof(float) * (size_t)C * (size_t)U);
-    L.kmt = take(sizeof(float) * (size_t)C * (size_t)U);
     L.u = need_u ? take(sizeof(float) * (size_t)C * (size_t)N) : o;
     L.w = need_w ? take(sizeof(float) * (size_t)nnz * (size_t)B) : o;
     L.total = o;
@@ -84,31 +84,33 @@ struct CdistParams {
   const float* e32; const uint16_t* e16; const float* en; const int* used; int64_t U;
   const float* q32; const uint16_t* q16; const float* qn; const int* qid; const int2* cinfo;
   int64_t C; int dp; float lam;
-  float* kt; float* kmt;
+  float* kt;
 };
 
 // One fused SDDMM-SpMM launch over the documents of one length bucket for one
 // query.  The same kernel runs every schedule; flags pick the variant.
 struct SinkParams {
   const float* kt;        // K^T block of the query: U rows x S floats
-  const float* kmt;       // (K .* M)^T block, same shape
   const float* r;         // S slots of the normalised query histogram (0 = unused slot)
   const int* vr;          // device: number of used slots (0 = invalid query)
-  const int64_t* doc_ptr; const int* wl; const float* wn;
-  const int* docs; int ndocs;
+  const int4* drec;       // documents of the bucket: (first entry lo, hi, length, id)
+  const int* wl; const float* wn;
+  int ndocs;
   int S;
+  float inv_lam;          // 1 / lambda: the final pass recovers M = -ln(K) / lambda
   float* out;             // row of this query, indexed by document id
   float* u;               // N x S scalings (per-iteration schedules), doc-major
   float* w;               // nnz sparse intermediate (unfused schedule)
   int iters;              // iterations run by this launch
   int load_u, store_u, do_final, store_w, load_w;
-  int lg_cg, lg_l;        // lane grid: 2^lg_cg column lanes, 2^lg_l lanes per document
 };
 
-// Register-resident shape (tc x tr cells per lane, lane grid 2^lg_cg x 2^(lg_l-lg_cg),
-// multiwave = more than 64 lanes per item) or, with `stream`, the one-block-per-item
-// fallback that re-reads K^T rows on every pass.
-struct SinkConfig { int tc, tr, lg_cg, lg_l; bool multiwave; bool stream; };
+// Register-resident shape: tc x tr cells per lane, 2^lg_cg column lanes, an item
+// spans `nwaves` waves of one block when multiwave (maxw = 4 or 16: the block
+// size the kernel was compiled for), else one wave with four items per block.
+// With `stream`: the one-block-per-item fallback that re-reads K^T rows on
+// every pass.
+struct SinkConfig { int tc, tr, lg_cg, nwaves; bool multiwave; bool stream; int maxw; };
 
 // --------------------------------------------------------- launch wrappers
 // Each returns the hipError_t of its launch.
@@ -125,12 +127,13 @@ hipError_t launch_prep_emb(const float* emb, int d, int dp, const int* used, int
                            float* e32, uint16_t* e16, float* en, hipStream_t s);
 
 hipError_t launch_select(const SelectParams& p, hipStream_t s);
-hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s);
+// `name` receives the kernel and tile shape that was launched.
+hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name);
 hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s);
 hipError_t launch_nan_docs(const int* docs, int64_t ndocs, float* out, hipStream_t s);
 
-// Host-side config choice for one (padded query width, bucket capacity) pair.
-bool choose_sink_config(int S, int cap, SinkConfig* cfg);
+// Host-side shape choice for one (padded query width, bucket capacity, documents) triple.
+bool choose_sink_config(int S, int cap, int ndocs, SinkConfig* cfg);
 bool sink_config_supported(const SinkConfig& cfg);
 int sink_grid(const SinkConfig& cfg, int ndocs);
 int sink_block(const SinkConfig& cfg);

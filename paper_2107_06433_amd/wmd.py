@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import numpy as np
 import torch
@@ -27,7 +27,8 @@ QUERY_ERRORS = {0: "ok", 1: "query word id out of range", 2: "query weight negat
 
 EXPORTS = [
     "wmd_corpus_workspace_bytes", "wmd_create_corpus", "wmd_get_corpus_info", "wmd_destroy",
-    "wmd_query_workspace_bytes", "wmd_query", "wmd_query_errors", "wmd_last_error",
+    "wmd_query_workspace_bytes", "wmd_query", "wmd_query_errors", "wmd_set_timing", "wmd_get_timing",
+    "wmd_last_error",
 ]
 
 
@@ -58,6 +59,13 @@ class QueryDesc(ctypes.Structure):
     ]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 96), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+        ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+    ]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2107_06433_amd.build`")
@@ -77,6 +85,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wmd_query.restype = i32
     lib.wmd_query_errors.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), vp]
     lib.wmd_query_errors.restype = i32
+    lib.wmd_set_timing.argtypes = [vp, i32]
+    lib.wmd_set_timing.restype = i32
+    lib.wmd_get_timing.argtypes = [vp, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.wmd_get_timing.restype = i32
     lib.wmd_last_error.argtypes = []
     lib.wmd_last_error.restype = ctypes.c_char_p
     return lib
@@ -119,6 +131,7 @@ class QueryBatch:
     q_ptr: torch.Tensor         # int64 [B+1], device
     ids: torch.Tensor           # int32 [T], device
     weights: torch.Tensor       # float32 [T], device
+    _ws_bytes: dict = field(default_factory=dict, repr=False)  # (corpus id, schedule) -> bytes
 
     @property
     def B(self) -> int:
@@ -199,10 +212,14 @@ class Corpus:
             pass
 
     def workspace_bytes(self, batch: QueryBatch, schedule: str = "auto") -> int:
-        n = lib().wmd_query_workspace_bytes(self._h, batch.B, batch.q_ptr_host.ctypes.data,
-                                            SCHEDULE[schedule])
-        if n == 0:
-            raise WMDError(1, lib().wmd_last_error().decode() or "invalid query batch")
+        key = (id(self), schedule)
+        n = batch._ws_bytes.get(key)
+        if n is None:
+            n = lib().wmd_query_workspace_bytes(self._h, batch.B, batch.q_ptr_host.ctypes.data,
+                                                SCHEDULE[schedule])
+            if n == 0:
+                raise WMDError(1, lib().wmd_last_error().decode() or "invalid query batch")
+            batch._ws_bytes[key] = n
         return n
 
     def query(self, batch: QueryBatch, lam: float, max_iter: int, cdist: str = "fp32",
@@ -233,6 +250,19 @@ class Corpus:
             if bad:
                 raise ValueError(f"invalid queries: {bad[:8]}")
         return out
+
+    def set_timing(self, enable: bool):
+        """Record HIP events around every kernel launch of later queries."""
+        _check(lib().wmd_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> list[dict]:
+        """Per-kernel launches, summed duration (ms) and algorithmic flops / bytes."""
+        cap = 64
+        arr = (KernelStat * cap)()
+        n = ctypes.c_int32()
+        _check(lib().wmd_get_timing(self._h, arr, cap, ctypes.byref(n)))
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
+                     flops=arr[i].flops, bytes=arr[i].bytes) for i in range(min(n.value, cap))]
 
     def query_errors(self, workspace: torch.Tensor, B: int, stream=None) -> np.ndarray:
         codes = np.zeros(B, dtype=np.int32)
