@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compact", action="store_true", help="cost matrix over the full vocabulary")
+    ap.add_argument("--untuned", action="store_true", help="ignore the measured shape table")
     return ap.parse_args()
 
 
@@ -135,7 +136,8 @@ def main():
     w = synth.make_workload(args.workload)
     c = w.corpus
     corpus = wmd.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, c.weights, device=dev,
-                                   compact_vocab=not args.no_compact)
+                                   compact_vocab=not args.no_compact,
+                                   tuning=None if args.untuned else wmd.TUNING_FILE)
     info = corpus.info()
     Q = w.queries
     if args.plain:
@@ -222,6 +224,7 @@ def main():
         "config": {"workload": describe(w, args.plain), "queries_per_step": Q.B, "docs": c.N,
                    "max_iter": w.max_iter, "cdist": args.cdist, "schedule": args.schedule,
                    "compact_vocab": not args.no_compact, "vocab_rows_U": info["U"],
+                   "tuned_shapes": corpus.pinned,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in s.items()} for s in stats],

@@ -183,6 +183,39 @@ wmd_status wmd_set_timing(wmd_corpus* c, int32_t enable);
  * (at most `capacity`) and their number to *count. */
 wmd_status wmd_get_timing(wmd_corpus* c, wmd_kernel_stat* stats, int32_t capacity, int32_t* count);
 
+/* One record per timed launch, in launch order: the kernel name, the padded
+ * query width S and length-bucket capacity of a Sinkhorn launch (0 for other
+ * kernels), its document count and the event-to-event duration. */
+typedef struct {
+  char name[96];
+  int32_t query, S, cap, ndocs;
+  double ms;
+} wmd_launch_rec;
+
+wmd_status wmd_get_launches(wmd_corpus* c, wmd_launch_rec* recs, int32_t capacity, int32_t* count);
+
+/* ------------------------------------------------------- kernel shapes */
+
+/* A shape of the fused Sinkhorn kernel: each lane keeps tc query words x tr
+ * document words of K^T in registers; 2^lg_cg lanes span the query words; a
+ * document occupies one wave (maxw = 1, four documents per block) or nwaves
+ * waves of a block compiled for at most maxw (4 or 16) waves.  stream = 1 is
+ * the fallback that re-reads K^T rows on every pass (other fields ignored). */
+typedef struct {
+  int32_t tc, tr, lg_cg, maxw, nwaves, stream;
+} wmd_sink_shape;
+
+/* The shapes that can run documents of up to `cap` words against a query of
+ * padded width S (a multiple of 4) on this corpus's device, best estimate of
+ * the built-in cost model first.  Writes at most `capacity`. */
+wmd_status wmd_sink_candidates(const wmd_corpus* c, int32_t S, int32_t cap, wmd_sink_shape* out, int32_t capacity,
+                               int32_t* count);
+
+/* Pins the shape this corpus uses for (S, cap), e.g. from a measured tuning
+ * table; NULL removes the pin.  A shape that cannot run (S, cap) is rejected
+ * with WMD_ERR_INVALID_ARGUMENT. */
+wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_sink_shape* shape);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* wmd_last_error(void);
 

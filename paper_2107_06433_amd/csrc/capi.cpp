@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -60,7 +61,7 @@ struct wmd_corpus {
   int* docs() const { return at<int>(ws, L.docs); }
 
   // per-launch timing (wmd_set_timing)
-  struct Rec { std::string name; size_t ev; double flops, bytes; };
+  struct Rec { std::string name; size_t ev; double flops, bytes; int query, S, cap, ndocs; };
   bool timing = false;
   std::vector<hipEvent_t> events;  // pool, reused; pairs (start, end)
   std::vector<Rec> recs;
@@ -73,6 +74,11 @@ struct wmd_corpus {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kSide] = {};
   std::mutex side_mu;  // one call at a time enqueues on the side streams
+
+  // Sinkhorn shapes pinned per (padded query width, bucket capacity)
+  std::map<std::pair<int, int>, SinkConfig> pinned;
+  // tag of the next timed launch (query, S, cap, ndocs)
+  int tag_query = -1, tag_S = 0, tag_cap = 0, tag_ndocs = 0;
 
   ~wmd_corpus() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -106,7 +112,7 @@ hipError_t timed_launch(wmd_corpus* c, hipStream_t s, const std::string& name, d
   if (err != hipSuccess) return err;
   err = hipEventRecord(c->events[ev + 1], s);
   if (err != hipSuccess) return err;
-  c->recs.push_back({name, ev, flops, bytes});
+  c->recs.push_back({name, ev, flops, bytes, c->tag_query, c->tag_S, c->tag_cap, c->tag_ndocs});
   return hipSuccess;
 }
 
@@ -330,6 +336,7 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
   sp.r = at<float>(ws, L.r); sp.cinfo = at<int2>(ws, L.cinfo); sp.qn = at<float>(ws, L.qn);
   sp.q32 = at<float>(ws, L.q32); sp.q16 = at<uint16_t>(ws, L.q16);
   sp.want_bf16 = q->cdist == WMD_CDIST_BF16;
+  c->tag_query = -1; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = 0;
   const double T = (double)q->q_ptr_host[q->B];  // raw query entries = sum of v_r
   const double esz = q->cdist == WMD_CDIST_BF16 ? 2.0 : 4.0;
   WMD_HIP(timed_launch(c, s, "select_kernel", 0.0, T * 8.0 + T * c->d * 4.0 + (double)plan.C * c->dp * (4.0 + esz),
@@ -380,9 +387,14 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
       const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
       if (nd == 0) continue;
       SinkConfig cfg{};
-      if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &cfg))
+      auto pin = c->pinned.find({S, kBucketCap[bk]});
+      if (pin != c->pinned.end()) {
+        cfg = pin->second;
+      } else if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &cfg)) {
         return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
                                                " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
+      }
+      c->tag_query = b; c->tag_S = S; c->tag_cap = kBucketCap[bk]; c->tag_ndocs = (int)nd;
       SinkParams p{};
       p.kt = kt + (size_t)col0 * (size_t)c->U;
       p.r = sp.r + col0;
@@ -439,6 +451,7 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
         WMD_HIP(go(f, fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd + 20.0 * ndd));
       }
     }
+      c->tag_query = b; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = (int)c->empty_count;
     if (c->empty_count > 0)
       WMD_HIP(timed_launch(c, s, "nan_docs_kernel", 0.0, 8.0 * c->empty_count,
                            [&] { return launch_nan_docs(c->docs() + c->empty_off, c->empty_count, orow, s); }));
@@ -485,6 +498,61 @@ wmd_status wmd_get_timing(wmd_corpus* c, wmd_kernel_stat* stats, int32_t capacit
   const int32_t n = (int32_t)acc.size();
   for (int32_t i = 0; i < n && i < capacity; ++i) stats[i] = acc[(size_t)i];
   *count = n;
+  return WMD_OK;
+}
+
+wmd_status wmd_get_launches(wmd_corpus* c, wmd_launch_rec* recs, int32_t capacity, int32_t* count) {
+  g_err.clear();
+  if (!c || !count || (capacity > 0 && !recs)) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL argument");
+  int32_t n = 0;
+  for (const auto& r : c->recs) {
+    if (n < capacity) {
+      WMD_HIP(hipEventSynchronize(c->events[r.ev + 1]));
+      float ms = 0.f;
+      WMD_HIP(hipEventElapsedTime(&ms, c->events[r.ev], c->events[r.ev + 1]));
+      wmd_launch_rec& o = recs[n];
+      std::memset(&o, 0, sizeof(o));
+      std::snprintf(o.name, sizeof(o.name), "%s", r.name.c_str());
+      o.query = r.query; o.S = r.S; o.cap = r.cap; o.ndocs = r.ndocs; o.ms = ms;
+    }
+    ++n;
+  }
+  *count = n;
+  return WMD_OK;
+}
+
+static wmd_sink_shape to_shape(const SinkConfig& c) {
+  wmd_sink_shape s{};
+  s.tc = c.tc; s.tr = c.tr; s.lg_cg = c.lg_cg; s.maxw = c.maxw; s.nwaves = c.nwaves; s.stream = c.stream ? 1 : 0;
+  return s;
+}
+
+wmd_status wmd_sink_candidates(const wmd_corpus* c, int32_t S, int32_t cap, wmd_sink_shape* out, int32_t capacity,
+                               int32_t* count) {
+  g_err.clear();
+  if (!c || !count || (capacity > 0 && !out)) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (S < 4 || S % 4 || cap < 1) return fail(WMD_ERR_INVALID_ARGUMENT, "S must be a positive multiple of 4, cap >= 1");
+  int bk = 0;
+  while (bk < kNumBuckets - 1 && kBucketCap[bk] < cap) ++bk;
+  const int nd = (int)(c->bucket_off[bk + 1] - c->bucket_off[bk]);
+  std::vector<SinkConfig> v(512);
+  const int n = sink_candidates(S, cap, nd > 0 ? nd : 1, v.data(), (int)v.size());
+  for (int i = 0; i < n && i < capacity && i < (int)v.size(); ++i) out[i] = to_shape(v[(size_t)i]);
+  *count = n;
+  return WMD_OK;
+}
+
+wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_sink_shape* shape) {
+  g_err.clear();
+  if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
+  if (!shape) {
+    c->pinned.erase({S, cap});
+    return WMD_OK;
+  }
+  SinkConfig cfg{shape->tc, shape->tr, shape->lg_cg, shape->nwaves, shape->maxw > 1, shape->stream != 0, shape->maxw};
+  if (cfg.stream) cfg = SinkConfig{0, 0, 6, 4, false, true, 4};
+  if (!sink_config_fits(cfg, S, cap)) return fail(WMD_ERR_INVALID_ARGUMENT, "shape cannot run this (S, cap)");
+  c->pinned[{S, cap}] = cfg;
   return WMD_OK;
 }
 

@@ -212,11 +212,27 @@ __global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParam
         acc[e] = a;
       }
       sum_high<LG_CG>(acc);
-      if constexpr (MW) {
-        // cross-wave sum in two phases: every wave posts its column partials,
-        // one thread per column adds them in wave order, every lane reads back
-        // its columns.  Both arrays alternate by iteration parity, so two
-        // barriers per iteration suffice.
+      if constexpr (MAXW == 4) {
+        // cross-wave sum for at most 4 waves: every wave posts its column
+        // partials, then each lane adds the partials of its own columns in wave
+        // order; the buffer alternates by iteration parity, one barrier each
+        float* part = lds + (it & 1) * nwaves * cw_stride;
+        if (lane < CG) {
+#pragma unroll
+          for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < TC; ++e) {
+          float a = 0.f;
+          for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + cg + CG * e];
+          acc[e] = a;
+        }
+      } else if constexpr (MW) {
+        // cross-wave sum in two phases for up to 16 waves: every wave posts its
+        // column partials, one thread per column adds them in wave order, every
+        // lane reads back its columns.  Both arrays alternate by iteration
+        // parity, so two barriers per iteration suffice.
         float* part = lds + (it & 1) * nwaves * cw_stride;
         float* tot = lds + 2 * nwaves * cw_stride + (it & 1) * cw_stride;
         if (lane < CG) {

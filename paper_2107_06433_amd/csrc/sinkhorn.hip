@@ -1,6 +1,9 @@
 // Launch side of the fused Sinkhorn kernels: the streaming fallback, the
 // table of instantiated register-resident shapes and the choice among them.
+#include <algorithm>
+#include <cmath>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "sink_kernel.h"
@@ -176,42 +179,85 @@ int sink_grid(const SinkConfig& c, int ndocs) {
 // on 1024 SIMDs the time is the larger of the issue-bound estimate
 // W I 4 / 1024 cycles and the latency-bound one: rounds of `occupancy`
 // resident waves per SIMD, each taking ~8 cycles per dependent instruction.
-bool choose_sink_config(int S, int cap, int ndocs, SinkConfig* out) {
-  double best = 1e300;
-  bool found = false;
+namespace {
+
+double model_cost(const Shape& sh, int nw, int ndocs) {
+  const SinkEntry& e = sh.e;
+  const bool mw = e.maxw > 1;
+  const int regs = (sh.regs + 7) & ~7;
+  int occ = 512 / regs;
+  occ = occ > 8 ? 8 : occ;
+  const double I = 2.0 * e.tr * e.tc + e.tr * e.lg_cg + e.tc * (6 - e.lg_cg) + 2.0 * e.tr + 2.0 * e.tc +
+                   (mw ? 2.0 * e.tc + nw + 20.0 * nw : 0.0);
+  const double waves = (double)ndocs * nw;
+  const double t_issue = waves * I * 4.0 / 1024.0;
+  const double rounds = std::ceil(waves / (1024.0 * occ));
+  const double t_lat = rounds * I * 8.0;
+  return t_issue > t_lat ? t_issue : t_lat;
+}
+
+// The waves per document a shape needs for `cap` rows, or 0 if it cannot hold them.
+int waves_for(const SinkEntry& e, int S, int cap) {
+  const int CG = 1 << e.lg_cg, RSW = 64 >> e.lg_cg;
+  if (e.tc * CG < S || (e.tc - 1) * CG >= S) return 0;  // the smallest tc that covers S
+  if (e.maxw == 1) {
+    if (RSW * e.tr < cap || (e.tr > 1 && RSW * (e.tr / 2) >= cap)) return 0;
+    return 1;
+  }
+  const int nw = (cap + RSW * e.tr - 1) / (RSW * e.tr);
+  return (nw < 2 || nw > e.maxw) ? 0 : nw;
+}
+
+}  // namespace
+
+bool sink_config_fits(const SinkConfig& c, int S, int cap) {
+  if (c.stream) return S <= kStreamMaxS && cap <= kMaxDocLen;
+  const Shape* sh = find_shape(c);
+  if (!sh || sh->spills) return false;
+  const int nw = waves_for(sh->e, S, cap);
+  return nw > 0 && nw == c.nwaves && lds_bytes(c) <= 65536;
+}
+
+// Cost model over the compiled shapes.  Per wave and iteration a shape
+// issues about I = 2 tr tc FMAs, tr lg_cg + tc (6 - lg_cg) DPP/permlane sums,
+// 2 instructions per row and per column for the reciprocals, and for
+// multi-wave items the two-phase LDS sum (about 2 tc + nwaves, plus barriers).
+// With W = items x nwaves waves on 1024 SIMDs the time is the larger of the
+// issue-bound estimate W I 4 / 1024 cycles and the latency-bound one: rounds
+// of `occupancy` resident waves per SIMD, ~8 cycles per dependent instruction.
+// Measured tuning tables override this choice per (S, cap).
+int sink_candidates(int S, int cap, int ndocs, SinkConfig* out, int max) {
+  std::vector<std::pair<double, SinkConfig>> all;
   for (const Shape& sh : shapes()) {
-    const SinkEntry& e = sh.e;
     if (sh.spills) continue;
-    const int CG = 1 << e.lg_cg, RSW = 64 >> e.lg_cg;
-    if (e.tc * CG < S || (e.tc - 1) * CG >= S) continue;  // the smallest tc that covers S
-    const bool mw = e.maxw > 1;
-    int nw = 1;
-    if (!mw) {
-      if (RSW * e.tr < cap || (e.tr > 1 && RSW * (e.tr / 2) >= cap)) continue;
-    } else {
-      nw = (cap + RSW * e.tr - 1) / (RSW * e.tr);
-      if (nw < 2 || nw > e.maxw) continue;
-    }
-    SinkConfig c{e.tc, e.tr, e.lg_cg, nw, mw, false, e.maxw};
+    const int nw = waves_for(sh.e, S, cap);
+    if (!nw) continue;
+    const bool mw = sh.e.maxw > 1;
+    SinkConfig c{sh.e.tc, sh.e.tr, sh.e.lg_cg, nw, mw, false, sh.e.maxw};
     if (lds_bytes(c) > 65536) continue;
     const int regs = (sh.regs + 7) & ~7;
-    int occ = 512 / regs;
-    occ = occ > 8 ? 8 : occ;
+    const int occ = 512 / regs > 8 ? 8 : 512 / regs;
     if (mw && (4 * occ) / nw < 1) continue;
-    const double I = 2.0 * e.tr * e.tc + e.tr * e.lg_cg + e.tc * (6 - e.lg_cg) + 2.0 * e.tr + 2.0 * e.tc +
-                     (mw ? 2.0 * e.tc + nw + 20.0 * nw : 0.0);
-    const double waves = (double)ndocs * nw;
-    const double t_issue = waves * I * 4.0 / 1024.0;
-    const double rounds = std::ceil(waves / (1024.0 * occ));
-    const double t_lat = rounds * I * 8.0;
-    const double cost = t_issue > t_lat ? t_issue : t_lat;
-    if (cost < best - 1e-9) { best = cost; *out = c; found = true; }
+    all.push_back({model_cost(sh, nw, ndocs), c});
   }
-  if (!found && S <= kStreamMaxS && cap <= kMaxDocLen) {
-    *out = SinkConfig{0, 0, 6, 4, false, true, 4};
-    found = true;
+  std::stable_sort(all.begin(), all.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  int n = 0;
+  for (const auto& a : all) {
+    if (n < max) out[n] = a.second;
+    ++n;
   }
-  return found;
+  if (S <= kStreamMaxS && cap <= kMaxDocLen) {
+    if (n < max) out[n] = SinkConfig{0, 0, 6, 4, false, true, 4};
+    ++n;
+  }
+  return n;
+}
+
+bool choose_sink_config(int S, int cap, int ndocs, SinkConfig* out) {
+  SinkConfig c[1];
+  if (sink_candidates(S, cap, ndocs, c, 1) < 1) return false;
+  *out = c[0];
+  return true;
 }
 
 hipError_t launch_sink(const SinkParams& p, const SinkConfig& c, int grid, hipStream_t s) {

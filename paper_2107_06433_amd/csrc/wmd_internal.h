@@ -132,9 +132,13 @@ hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const ch
 hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s);
 hipError_t launch_nan_docs(const int* docs, int64_t ndocs, float* out, hipStream_t s);
 
-// Host-side shape choice for one (padded query width, bucket capacity, documents) triple.
+// Host-side shape choice for one (padded query width, bucket capacity, documents)
+// triple: feasible shapes by increasing model cost (the streaming fallback last).
+int sink_candidates(int S, int cap, int ndocs, SinkConfig* out, int max);
 bool choose_sink_config(int S, int cap, int ndocs, SinkConfig* cfg);
 bool sink_config_supported(const SinkConfig& cfg);
+// Whether `cfg` can run documents of up to `cap` words at padded query width S.
+bool sink_config_fits(const SinkConfig& cfg, int S, int cap);
 int sink_grid(const SinkConfig& cfg, int ndocs);
 int sink_block(const SinkConfig& cfg);
 

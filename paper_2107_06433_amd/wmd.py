@@ -28,8 +28,9 @@ QUERY_ERRORS = {0: "ok", 1: "query word id out of range", 2: "query weight negat
 EXPORTS = [
     "wmd_corpus_workspace_bytes", "wmd_create_corpus", "wmd_get_corpus_info", "wmd_destroy",
     "wmd_query_workspace_bytes", "wmd_query", "wmd_query_errors", "wmd_set_timing", "wmd_get_timing",
-    "wmd_last_error",
+    "wmd_get_launches", "wmd_sink_candidates", "wmd_set_sink_shape", "wmd_last_error",
 ]
+TUNING_FILE = os.path.join(_PKG, "tuning", "gfx950_sink_shapes.json")
 
 
 class CorpusDesc(ctypes.Structure):
@@ -66,6 +67,20 @@ class KernelStat(ctypes.Structure):
     ]
 
 
+class LaunchRec(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 96), ("query", ctypes.c_int32), ("S", ctypes.c_int32),
+        ("cap", ctypes.c_int32), ("ndocs", ctypes.c_int32), ("ms", ctypes.c_double),
+    ]
+
+
+class SinkShape(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("tc", "tr", "lg_cg", "maxw", "nwaves", "stream")]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2107_06433_amd.build`")
@@ -89,6 +104,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wmd_set_timing.restype = i32
     lib.wmd_get_timing.argtypes = [vp, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(ctypes.c_int32)]
     lib.wmd_get_timing.restype = i32
+    lib.wmd_get_launches.argtypes = [vp, ctypes.POINTER(LaunchRec), i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.wmd_get_launches.restype = i32
+    lib.wmd_sink_candidates.argtypes = [vp, i32, i32, ctypes.POINTER(SinkShape), i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.wmd_sink_candidates.restype = i32
+    lib.wmd_set_sink_shape.argtypes = [vp, i32, i32, ctypes.POINTER(SinkShape)]
+    lib.wmd_set_sink_shape.restype = i32
     lib.wmd_last_error.argtypes = []
     lib.wmd_last_error.restype = ctypes.c_char_p
     return lib
@@ -161,7 +182,8 @@ class Corpus:
     """A resident corpus: embeddings (V x d) and documents in CSC form, on one GPU."""
 
     def __init__(self, emb: torch.Tensor, doc_ptr: torch.Tensor, word_ids: torch.Tensor,
-                 weights: torch.Tensor, compact_vocab: bool = True, stream=None):
+                 weights: torch.Tensor, compact_vocab: bool = True, stream=None,
+                 tuning: str | None = TUNING_FILE):
         if not emb.is_cuda:
             raise ValueError("emb must be a device tensor")
         self.emb = emb.contiguous().to(torch.float32)
@@ -185,12 +207,69 @@ class Corpus:
             _check(lib().wmd_create_corpus(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(handle)))
         self._h = handle
         self.V, self.d, self.N, self.nnz = V, d, N, nnz
+        self.pinned = 0
+        if tuning and os.path.exists(tuning):
+            self.load_tuning(tuning)
 
     @classmethod
-    def from_numpy(cls, emb, doc_ptr, word_ids, weights, device="cuda", compact_vocab=True):
+    def from_numpy(cls, emb, doc_ptr, word_ids, weights, device="cuda", compact_vocab=True,
+                   tuning: str | None = TUNING_FILE):
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
         return cls(t(emb, torch.float32), t(doc_ptr, torch.int64), t(word_ids, torch.int32),
-                   t(weights, torch.float32), compact_vocab=compact_vocab)
+                   t(weights, torch.float32), compact_vocab=compact_vocab, tuning=tuning)
+
+    # ---- kernel shapes (measured tuning)
+    def sink_candidates(self, S: int, cap: int) -> list[dict]:
+        arr = (SinkShape * 512)()
+        n = ctypes.c_int32()
+        _check(lib().wmd_sink_candidates(self._h, S, cap, arr, 512, ctypes.byref(n)))
+        return [arr[i].as_dict() for i in range(min(n.value, 512))]
+
+    def set_sink_shape(self, S: int, cap: int, shape: dict | None) -> None:
+        if shape is None:
+            _check(lib().wmd_set_sink_shape(self._h, S, cap, None))
+        else:
+            _check(lib().wmd_set_sink_shape(self._h, S, cap, ctypes.byref(SinkShape(**shape))))
+
+    def load_tuning(self, path: str) -> int:
+        """Pin shapes from a measured tuning table; returns how many were applied.
+
+        Entries are keyed by (S, bucket capacity, log2 of the bucket's document
+        count); for each (S, cap) the entry tuned on the nearest document count
+        to this corpus's bucket is used.
+        """
+        import json
+        import math
+        with open(path) as f:
+            table = json.load(f)
+        info = self.info()
+        docs = dict(zip(info["bucket_cap"], info["bucket_docs"]))
+        best = {}
+        for ent in table.get("entries", []):
+            key = (int(ent["S"]), int(ent["cap"]))
+            nd = docs.get(key[1], 0)
+            if nd <= 0:
+                continue
+            dist = abs(int(ent.get("ndocs_log2", 0)) - int(math.floor(math.log2(nd))))
+            if key not in best or dist < best[key][0]:
+                best[key] = (dist, ent["shape"])
+        n = 0
+        for (S, cap), (_, shape) in best.items():
+            try:
+                self.set_sink_shape(S, cap, shape)
+                n += 1
+            except WMDError:
+                pass  # a shape this build cannot run for that key: keep the model's choice
+        self.pinned = n
+        return n
+
+    def launches(self) -> list[dict]:
+        cap = 1 << 16
+        arr = (LaunchRec * cap)()
+        n = ctypes.c_int32()
+        _check(lib().wmd_get_launches(self._h, arr, cap, ctypes.byref(n)))
+        return [dict(name=arr[i].name.decode(), query=arr[i].query, S=arr[i].S, cap=arr[i].cap,
+                     ndocs=arr[i].ndocs, ms=arr[i].ms) for i in range(min(n.value, cap))]
 
     def info(self) -> dict:
         info = CorpusInfo()
