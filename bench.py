@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--sweep", type=float, nargs="*", default=[], help="serving: extra arrival rates to try")
     ap.add_argument("--mem-budget-gb", type=float, default=24.0, help="serving: device memory for queries")
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scale for HBM counters)")
     return ap.parse_args()
 
 
@@ -208,6 +210,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}))
+        return
     if args.workload == "serving":
         serving(args)
         return
