@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-compact", action="store_true", help="cost matrix over the full vocabulary")
     ap.add_argument("--untuned", action="store_true", help="ignore the measured shape table")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="stop each document once x changes by at most tol (max_iter is the cap); "
+                         "the value then counts the iterations actually run")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate (queries/s)")
     ap.add_argument("--serve-queries", type=int, default=20000, help="serving: measured queries")
     ap.add_argument("--serve-warmup", type=int, default=2000, help="serving: warm-up queries")
@@ -235,12 +238,13 @@ def main():
     else:
         batches = [wmd.QueryBatch.from_arrays(Q.q_ptr, Q.ids, Q.weights, device=dev)]
     outs = [torch.empty((bt.B, c.N), dtype=torch.float32, device=dev) for bt in batches]
+    itss = [torch.zeros((bt.B, c.N), dtype=torch.int32, device=dev) if args.tol > 0 else None for bt in batches]
     wss = [torch.empty(corpus.workspace_bytes(bt, args.schedule), dtype=torch.uint8, device=dev) for bt in batches]
 
     def step():
-        for bt, o, ws in zip(batches, outs, wss):
+        for bt, o, ws, its in zip(batches, outs, wss, itss):
             corpus.query(bt, w.lam, w.max_iter, cdist=args.cdist, schedule=args.schedule, out=o,
-                         workspace=ws, check=False)
+                         workspace=ws, check=False, tol=args.tol, iters=its)
 
     # validity check of the configuration before timing
     step()
@@ -261,6 +265,8 @@ def main():
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
     docs_iters = Q.B * c.N * w.max_iter
+    if args.tol > 0:  # the iterations actually executed (every step runs the same ones)
+        docs_iters = int(sum(int(its.sum().item()) for its in itss))
     value = docs_iters / (ms / 1e3)
     print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step", file=sys.stderr, flush=True)
 
@@ -312,7 +318,7 @@ def main():
         "vs_baseline": None, "dtype": "f32" if args.cdist == "fp32" else "bf16-gemm+f32",
         "data": "synthetic (seeded Zipf corpus and N(0,1/d) embeddings; no dataset)",
         "config": {"workload": describe(w, args.plain), "queries_per_step": Q.B, "docs": c.N,
-                   "max_iter": w.max_iter, "cdist": args.cdist, "schedule": args.schedule,
+                   "max_iter": w.max_iter, "cdist": args.cdist, "schedule": args.schedule, "tol": args.tol,
                    "compact_vocab": not args.no_compact, "vocab_rows_U": info["U"],
                    "tuned_shapes": corpus.pinned,
                    "parallelism": "single GPU"},

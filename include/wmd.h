@@ -137,6 +137,12 @@ typedef struct {
   int32_t max_iter;           /* Sinkhorn-Knopp iterations, 0..100000                  */
   int32_t cdist;              /* wmd_cdist                                             */
   int32_t schedule;           /* wmd_schedule                                          */
+  float tol;                  /* 0: exactly max_iter iterations (the paper's cut-off).
+                                 > 0: a document stops as soon as an iteration changes
+                                 its x by at most tol, max_i |x_new_i - x_i| / x_new_i
+                                 <= tol ("while x changes", Algorithm 1), and at
+                                 max_iter at the latest.  Resident schedule only.       */
+  int32_t* iters;             /* device, B*N int32 or NULL: iterations each document ran */
 } wmd_query_desc;
 
 /* Bytes of query workspace for B queries with these offsets and schedule

@@ -21,6 +21,7 @@ from .wmd import (  # noqa: F401
     normalized_columns,
     cost_rows,
     sinkhorn_scalings,
+    sinkhorn_scalings_until,
     sinkhorn_wmd_dense,
     sinkhorn_wmd_support,
     transport_plan,

@@ -116,6 +116,35 @@ def sinkhorn_scalings(r, M, c, lam: float, max_iter: int):
     return u, v, K
 
 
+def sinkhorn_scalings_until(r, M, c, lam: float, max_iter: int, tol: float):
+    """Algorithm 1 with its "while x changes" loop for one document column.
+
+    Iterates as ``sinkhorn_scalings`` but stops after the first iteration whose
+    relative change of x, max_i |x_new_i - x_i| / x_new_i, is at most ``tol``
+    (at ``max_iter`` iterations at the latest).  Returns ``(u, v, K, iters)``.
+    """
+    r = np.asarray(r, dtype=np.float64)
+    M = np.asarray(M, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64).reshape(-1, 1)
+    K = np.exp(-lam * M)
+    x = np.ones((r.shape[0], 1), dtype=np.float64) / r.shape[0]
+    mask = c > 0
+    done = 0
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        for it in range(max_iter):
+            u = 1.0 / x
+            v = np.where(mask, c / (K.T @ u), 0.0)
+            x_new = (1.0 / r)[:, None] * (K @ v)
+            change = np.max(np.abs(x_new - x) / x_new)
+            x = x_new
+            done = it + 1
+            if change <= tol:
+                break
+        u = 1.0 / x
+        v = np.where(mask, c / (K.T @ u), 0.0)
+    return u, v, K, done
+
+
 def sinkhorn_wmd_dense(r, M, c, lam: float, max_iter: int) -> np.ndarray:
     """``d_M^lambda(r, c) = sum(u .* ((K .* M) v))`` per column (Algorithm 1, last line)."""
     u, v, K = sinkhorn_scalings(r, M, c, lam, max_iter)
@@ -152,13 +181,15 @@ def wmd_dense_corpus(E, doc_ptr, word_ids, weights, q_ids, q_weights, lam: float
 
 
 def sinkhorn_wmd_support(E, doc_ptr, word_ids, weights, q_ids, q_weights, lam: float,
-                         max_iter: int, docs=None) -> np.ndarray:
+                         max_iter: int, docs=None, tol: float | None = None):
     """The same iteration restricted to each document's own words.
 
     For document k only the rows of ``c`` with ``c_jk > 0`` take part (every
     other entry of v is zero), so Algorithm 1 reduces to Cuturi's Sinkhorn on
     the v_r x n_k cost matrix ``M[:, words of k]``.  Documents are processed
-    one at a time with the dense routine above on that small problem.
+    one at a time with the dense routine above on that small problem.  With
+    ``tol`` each document stops as ``sinkhorn_scalings_until`` does, and the
+    iteration counts are returned as a second array.
     """
     E = np.asarray(E)
     V = E.shape[0]
@@ -168,6 +199,7 @@ def sinkhorn_wmd_support(E, doc_ptr, word_ids, weights, q_ids, q_weights, lam: f
     N = len(doc_ptr) - 1
     docs = np.arange(N) if docs is None else np.asarray(docs, dtype=np.int64)
     out = np.empty(len(docs), dtype=np.float64)
+    its = np.zeros(len(docs), dtype=np.int64)
     for n, k in enumerate(docs):
         s, e = doc_ptr[k], doc_ptr[k + 1]
         ids = np.asarray(word_ids[s:e], dtype=np.int64)
@@ -186,5 +218,10 @@ def sinkhorn_wmd_support(E, doc_ptr, word_ids, weights, q_ids, q_weights, lam: f
         Ed = np.asarray(E[uid], dtype=np.float64)
         diff = Eq[:, None, :] - Ed[None, :, :]
         Md = np.sqrt(np.einsum("ijt,ijt->ij", diff, diff))
-        out[n] = sinkhorn_wmd_dense(r, Md, cw[:, None], lam, max_iter)[0]
-    return out
+        if tol is None:
+            out[n] = sinkhorn_wmd_dense(r, Md, cw[:, None], lam, max_iter)[0]
+        else:
+            u, v, K, its[n] = sinkhorn_scalings_until(r, Md, cw, lam, max_iter, tol)
+            with np.errstate(invalid="ignore", over="ignore"):
+                out[n] = np.sum(u * ((K * Md) @ v), axis=0)[0]
+    return out if tol is None else (out, its)

@@ -313,6 +313,9 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
   if (q->max_iter < 0 || q->max_iter > 100000) return fail(WMD_ERR_INVALID_ARGUMENT, "max_iter must be in [0, 100000]");
   if (q->cdist != WMD_CDIST_FP32 && q->cdist != WMD_CDIST_BF16) return fail(WMD_ERR_INVALID_ARGUMENT, "unknown cdist precision");
   if (q->schedule < WMD_SCHEDULE_AUTO || q->schedule > WMD_SCHEDULE_UNFUSED) return fail(WMD_ERR_INVALID_ARGUMENT, "unknown schedule");
+  if (!(q->tol >= 0.f) || !std::isfinite(q->tol)) return fail(WMD_ERR_INVALID_ARGUMENT, "tol must be finite and >= 0");
+  if (q->tol > 0.f && q->schedule != WMD_SCHEDULE_AUTO && q->schedule != WMD_SCHEDULE_RESIDENT)
+    return fail(WMD_ERR_NOT_SUPPORTED, "a tolerance stop needs the resident schedule");
   QueryPlan plan;
   wmd_status st = plan_query(c, q->B, q->q_ptr_host, &plan);
   if (st != WMD_OK) return st;
@@ -362,6 +365,13 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
     if (c->recs.size() > nrec) c->recs.back().name = name;
   }
 
+  // iterations per document: 0 for documents that are never iterated (no
+  // positive weight); the Sinkhorn launches overwrite the others
+  if (q->iters) {
+    const int64_t n = (int64_t)q->B * c->N;
+    WMD_HIP(launch_fill_i32(q->iters, n, schedule == WMD_SCHEDULE_RESIDENT ? 0 : q->max_iter, s));
+  }
+
   // a4-a6: Sinkhorn iterations and the final pass, per query and length bucket.
   // Each (query, bucket) group is independent of the others; with more than
   // one group they are spread over the side streams.
@@ -404,6 +414,8 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
       p.ndocs = (int)nd;
       p.S = S;
       p.inv_lam = 1.0f / q->lambda;
+      p.tol = q->tol;
+      p.iters_out = (q->iters && schedule == WMD_SCHEDULE_RESIDENT) ? q->iters + (size_t)b * (size_t)c->N : nullptr;
       p.out = orow;
       p.u = ubuf + (size_t)col0 * (size_t)c->N;
       p.w = wbuf + (size_t)b * (size_t)c->nnz;

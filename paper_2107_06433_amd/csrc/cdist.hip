@@ -187,14 +187,15 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
 // Few query columns (C <= 32): the GEMM is a stream over the U x dp vocabulary
 // rows.  Each wave owns 16 rows and reads them straight from memory into the
 // MFMA operand registers -- for every 16 (f32) or 32 (bf16) k values, the four
-// lane quads of a row read one contiguous 64-byte piece -- with a chunk of
-// loads kept in flight ahead of the MFMAs.  Q (at most 32 rows) is staged once
-// per block in LDS.
+// lane quads of a row read one contiguous 64-byte piece.  All loads of a row
+// (up to 24 steps) are issued at once, before Q (at most 32 rows) is staged in
+// LDS and before the epilogue's per-row data is fetched, so one memory latency
+// covers the whole row.
 template <int NT, bool BF16>
 __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   constexpr int ESZ = BF16 ? 2 : 4;
   constexpr int KS = BF16 ? 32 : 16;        // k values per 16-byte-per-lane load step
-  constexpr int CH = 8;                     // load steps per chunk
+  constexpr int CH = 24;                    // load steps per chunk: a whole row for dp <= 384 (f32) / 768 (bf16)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int dp = p.dp;
@@ -216,6 +217,15 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
       buf[i] = (row_ok && s0 + i < nsteps) ? *(const uint4*)(Ag + (size_t)(s0 + i) * 64) : make_uint4(0, 0, 0, 0);
   };
   load(0);  // the first vocabulary loads are in flight while Q is staged
+  // the epilogue's per-row data, fetched early for the same reason
+  float en_r[4];
+  int used_r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t m = m0 + 4 * (lane >> 4) + i;
+    en_r[i] = m < p.U ? p.en[m] : 0.f;
+    used_r[i] = m < p.U ? p.used[m] : -1;
+  }
   // stage Q: NT*16 rows (zero beyond C)
   const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
   const int vpr = dp * ESZ / 16;
@@ -227,10 +237,7 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   }
   __syncthreads();
   for (int s0 = 0; s0 < nsteps; s0 += CH) {
-    uint4 cur[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) cur[i] = buf[i];
-    if (s0 + CH < nsteps) load(s0 + CH);
+    if (s0 > 0) load(s0);  // rows longer than one chunk: next chunk after this one's MFMAs
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
       if (s0 + i >= nsteps) break;
@@ -239,10 +246,10 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
       for (int t = 0; t < NT; ++t) {
         const uint4 q = *(const uint4*)(smem + (t * 16 + (lane & 15)) * ldq + kb);
         if constexpr (BF16) {
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[i]),
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, buf[i]),
                                                           __builtin_bit_cast(bf16x8, q), acc[t], 0, 0, 0);
         } else {
-          const f32x4 a = __builtin_bit_cast(f32x4, cur[i]);
+          const f32x4 a = __builtin_bit_cast(f32x4, buf[i]);
           const f32x4 b = __builtin_bit_cast(f32x4, q);
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[t], 0, 0, 0);
@@ -265,8 +272,8 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
       if (m >= p.U) continue;
       float kv = 0.f;
       if (q >= 0) {
-        const float m2 = p.en[m] + qn - 2.f * acc[t][i];
-        const float dist = p.used[m] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
+        const float m2 = en_r[i] + qn - 2.f * acc[t][i];
+        const float dist = used_r[i] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
         kv = expf(-p.lam * dist);
       }
       kt[(size_t)m * ci.y] = kv;

@@ -31,6 +31,16 @@ __device__ __forceinline__ float dpp(float x) {
 // ~10 instructions for the IEEE division sequence.
 __device__ __forceinline__ float fast_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// max(x[l], x[l ^ 16]) and max(x[l], x[l ^ 32])
+__device__ __forceinline__ float max_xor16(float x) {
+  auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+}
+__device__ __forceinline__ float max_xor32(float x) {
+  auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+}
+
 // x[l] + x[l ^ 16]
 __device__ __forceinline__ float add_xor16(float x) {
   auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);

@@ -186,13 +186,25 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
     const int q = i >= 0 ? s_id[i] : -1;
     const float* src = p.emb + (size_t)(q < 0 ? 0 : q) * p.d;
     double nrm = 0.0;
-    if (s < S)
-      for (int k = lane8; k < p.dp; k += 8) {
-        const float x = (q >= 0 && k < p.d) ? src[k] : 0.f;
-        p.q32[(size_t)(col0 + s) * p.dp + k] = x;
-        if (p.want_bf16) p.q16[(size_t)(col0 + s) * p.dp + k] = f32_to_bf16(x);
-        nrm += (double)x * (double)x;
+    if (s < S) {
+      // dp is a multiple of 64: 8 values per lane per round, all loads of a
+      // round issued before any is used
+      for (int k0 = 0; k0 < p.dp; k0 += 64) {
+        float x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = k0 + lane8 + 8 * i;
+          x[i] = (q >= 0 && k < p.d) ? src[k] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = k0 + lane8 + 8 * i;
+          p.q32[(size_t)(col0 + s) * p.dp + k] = x[i];
+          if (p.want_bf16) p.q16[(size_t)(col0 + s) * p.dp + k] = f32_to_bf16(x[i]);
+          nrm += (double)x[i] * (double)x[i];
+        }
       }
+    }
     nrm += __shfl_xor(nrm, 1, 8);
     nrm += __shfl_xor(nrm, 2, 8);
     nrm += __shfl_xor(nrm, 4, 8);

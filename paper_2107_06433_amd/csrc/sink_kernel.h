@@ -95,6 +95,18 @@ __device__ __forceinline__ void sum_high(float (&x)[N]) {
   }
 }
 
+// Maximum over lane bits [0, NB), lower bits first (as sum_low).
+template <int NB>
+__device__ __forceinline__ float max_low(float x) {
+  if constexpr (NB > 0) x = fmaxf(x, dpp<kDppXor1>(x));
+  if constexpr (NB > 1) x = fmaxf(x, dpp<kDppXor2>(x));
+  if constexpr (NB > 2) x = fmaxf(x, dpp<kDppHalfMirror>(x));
+  if constexpr (NB > 3) x = fmaxf(x, dpp<kDppMirror>(x));
+  if constexpr (NB > 4) x = max_xor16(x);
+  if constexpr (NB > 5) x = max_xor32(x);
+  return x;
+}
+
 // The cost M of a kernel entry K = exp(-lambda M), recovered as -ln(K) / lambda.
 // K = 1 (the same word) gives exactly 0; an entry at or below the smallest
 // normal float contributes K * M ~ 0 and is dropped.
@@ -179,6 +191,7 @@ __global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParam
     }
 
     // ---- Sinkhorn-Knopp iterations
+    int ran = p.iters;
     for (int it = 0; it < p.iters; ++it) {
       if (!p.load_w) {
         float s[TR];
@@ -249,6 +262,24 @@ __global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParam
 #pragma unroll
         for (int e = 0; e < TC; ++e) acc[e] = tot[cg + CG * e];
       }
+      if (p.tol > 0.f) {
+        // "while x changes": x = 1/u, so |x_new - x| / x_new = |u - u_new| / u.
+        // Every lane of the item holds the same u, so the decision is uniform
+        // over the item's waves.
+        float dm = 0.f;
+#pragma unroll
+        for (int e = 0; e < TC; ++e) {
+          const float un = fast_div(rv[e], acc[e]);
+          if (rv[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un) * __builtin_amdgcn_rcpf(u[e]));
+          u[e] = un;
+        }
+        dm = max_low<LG_CG>(dm);
+        if (!(dm > p.tol)) {
+          ran = it + 1;
+          break;
+        }
+        continue;
+      }
 #pragma unroll
       for (int e = 0; e < TC; ++e) u[e] = fast_div(rv[e], acc[e]);
     }
@@ -294,7 +325,10 @@ __global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParam
         tot = a;
         __syncthreads();
       }
-      if (lane == 0 && (MW ? wave == 0 : true) && active) p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
+      if (lane == 0 && (MW ? wave == 0 : true) && active) {
+        p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
+        if (p.iters_out) p.iters_out[k] = ran;
+      }
     }
   }
 }

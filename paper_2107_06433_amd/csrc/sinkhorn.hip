@@ -107,6 +107,7 @@ __global__ void __launch_bounds__(256) sink_stream_kernel(SinkParams p) {
       if (threadIdx.x == 0) {
         const float tot = ((sred[0] + sred[1]) + sred[2]) + sred[3];
         p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
+        if (p.iters_out) p.iters_out[k] = p.iters;  // no tolerance stop on this path
       }
     }
     __syncthreads();

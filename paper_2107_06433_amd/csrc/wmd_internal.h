@@ -101,8 +101,10 @@ struct SinkParams {
   float* out;             // row of this query, indexed by document id
   float* u;               // N x S scalings (per-iteration schedules), doc-major
   float* w;               // nnz sparse intermediate (unfused schedule)
-  int iters;              // iterations run by this launch
+  int iters;              // iterations run by this launch (the cap when tol > 0)
   int load_u, store_u, do_final, store_w, load_w;
+  float tol;              // > 0: stop a document once max_i |dx_i| / x_i <= tol
+  int* iters_out;         // per document of this query (indexed by id), or null
 };
 
 // Register-resident shape: tc x tr cells per lane, 2^lg_cg column lanes, an item

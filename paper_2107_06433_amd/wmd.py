@@ -57,6 +57,7 @@ class QueryDesc(ctypes.Structure):
         ("B", ctypes.c_int32), ("q_ptr_host", ctypes.c_void_p), ("q_ptr", ctypes.c_void_p),
         ("q_ids", ctypes.c_void_p), ("q_weights", ctypes.c_void_p), ("lam", ctypes.c_float),
         ("max_iter", ctypes.c_int32), ("cdist", ctypes.c_int32), ("schedule", ctypes.c_int32),
+        ("tol", ctypes.c_float), ("iters", ctypes.c_void_p),
     ]
 
 
@@ -303,7 +304,8 @@ class Corpus:
 
     def query(self, batch: QueryBatch, lam: float, max_iter: int, cdist: str = "fp32",
               schedule: str = "auto", out: torch.Tensor | None = None,
-              workspace: torch.Tensor | None = None, stream=None, check: bool = True) -> torch.Tensor:
+              workspace: torch.Tensor | None = None, stream=None, check: bool = True,
+              tol: float = 0.0, iters: torch.Tensor | None = None) -> torch.Tensor:
         """Distances of every query to every document: float32 [B, N] on the device.
 
         With ``check`` the call waits for the stream and raises ValueError if a
@@ -315,9 +317,12 @@ class Corpus:
         need = self.workspace_bytes(batch, schedule)
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if iters is not None and (iters.dtype != torch.int32 or iters.numel() < B * self.N or not iters.is_cuda):
+            raise ValueError("iters must be a device int32 tensor of B*N elements")
         desc = QueryDesc(B=B, q_ptr_host=batch.q_ptr_host.ctypes.data, q_ptr=_ptr(batch.q_ptr),
                          q_ids=_ptr(batch.ids), q_weights=_ptr(batch.weights), lam=float(lam),
-                         max_iter=int(max_iter), cdist=CDIST[cdist], schedule=SCHEDULE[schedule])
+                         max_iter=int(max_iter), cdist=CDIST[cdist], schedule=SCHEDULE[schedule],
+                         tol=float(tol), iters=_ptr(iters))
         sh = _stream_handle(stream)
         with torch.cuda.device(self.device):
             _check(lib().wmd_query(self._h, ctypes.byref(desc), _ptr(out), _ptr(workspace),

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 def test_ctypes_structs_match_header_layout():
     # sizes implied by the C declarations on LP64
     assert ctypes.sizeof(wmd.CorpusDesc) == 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(wmd.QueryDesc) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(wmd.QueryDesc) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 8
     assert ctypes.sizeof(wmd.CorpusInfo) == 3 * 8 + 2 * 4 + 8 + 8 + 8 + 16 * 8 + 16 * 4
 
 
@@ -78,7 +78,8 @@ def test_query_descriptor_validation_messages():
     # a non-NULL but fake corpus pointer is never dereferenced before the
     # descriptor checks fail
     fake = ctypes.c_void_p(1)
-    for field, value in [("lam", 0.0), ("lam", float("nan")), ("max_iter", -1), ("cdist", 7), ("schedule", 9)]:
+    for field, value in [("lam", 0.0), ("lam", float("nan")), ("max_iter", -1), ("cdist", 7), ("schedule", 9),
+                         ("tol", -1.0), ("tol", float("inf"))]:
         q = wmd.QueryDesc(B=1, q_ptr_host=1, q_ptr=1, q_ids=1, q_weights=1, lam=10.0,
                           max_iter=15, cdist=0, schedule=0)
         setattr(q, field, value)

@@ -297,3 +297,33 @@ def test_corpus_validation_errors(W):
     long = handmade_corpus(rng, 9000, 8, [4097], dup=True)
     with pytest.raises(W.WMDError):
         W.Corpus.from_numpy(long.emb, long.doc_ptr, long.word_ids, long.weights)
+
+
+# ------------------------------------------------------- "while x changes" stop
+
+@pytest.mark.parametrize("tol", [1e-2, 1e-4])
+def test_tolerance_stop_counts_and_values(W, single, tol):
+    """The GPU decides each document's iteration count k in float32.  k must
+    lie between the oracle's counts at tol*1.1 and tol*0.9 (the decision may
+    flip within rounding of the threshold), and the distance must match the
+    oracle run for exactly k iterations."""
+    c = single.corpus
+    corpus = corpus_of(W, c)
+    batch = W.QueryBatch.from_arrays(single.queries.q_ptr, single.queries.ids, single.queries.weights)
+    iters = torch.zeros(c.N, dtype=torch.int32, device="cuda")
+    got = corpus.query(batch, single.lam, 200, tol=tol, iters=iters)
+    torch.cuda.synchronize()
+    got, k = got.cpu().numpy()[0], iters.cpu().numpy()
+    docs = sample_docs(c.N, seed=4)[:80]
+    ids, qw = single.queries.query(0)
+    _, k_hi = oracle.sinkhorn_wmd_support(c.emb, c.doc_ptr, c.word_ids, c.weights, ids, qw, single.lam, 200,
+                                          docs=docs, tol=tol * 0.9)
+    _, k_lo = oracle.sinkhorn_wmd_support(c.emb, c.doc_ptr, c.word_ids, c.weights, ids, qw, single.lam, 200,
+                                          docs=docs, tol=tol * 1.1)
+    kd = k[docs]
+    assert np.all(kd >= 1) and np.all(kd <= 200)  # documents may run up to the cap
+    assert np.all((k_lo <= kd) & (kd <= k_hi)), list(zip(k_lo, kd, k_hi))
+    for kk in np.unique(kd):
+        sel = docs[kd == kk]
+        ref = oracle_support(c, ids, qw, single.lam, int(kk), sel)
+        assert_close(got[sel], ref, TOL32, f"tol={tol} k={kk}")

@@ -335,3 +335,43 @@ def test_one_iteration_closed_form(seed):
     v = c / (K.T @ u)
     want = float((u[:, None] * K * M * v[None, :]).sum())
     assert abs(one_doc(E, q, qw, ids, w, lam, 1) - want) <= 1e-13 * want
+
+
+# --- the "while x changes" stop --------------------------------------------------------
+
+def test_tolerance_stop_consistency():
+    """tol = 0 runs every iteration; a huge tol stops after one; the count
+    grows as tol shrinks, the stopping iteration is the first whose change of
+    x is within tol, and the distance approaches the long-run value."""
+    rng = np.random.default_rng(51)
+    E, ptr, ids, w, q, qw = small_corpus(rng, N=6)
+    fixed15 = oracle.sinkhorn_wmd_support(E, ptr, ids, w, q, qw, 10.0, 15)
+    a, it_a = oracle.sinkhorn_wmd_support(E, ptr, ids, w, q, qw, 10.0, 15, tol=0.0)
+    np.testing.assert_allclose(a, fixed15, rtol=1e-14)
+    assert np.all(it_a == 15)
+    one = oracle.sinkhorn_wmd_support(E, ptr, ids, w, q, qw, 10.0, 1)
+    b, it_b = oracle.sinkhorn_wmd_support(E, ptr, ids, w, q, qw, 10.0, 15, tol=1e30)
+    np.testing.assert_allclose(b, one, rtol=1e-14)
+    assert np.all(it_b == 1)
+    long_run = oracle.sinkhorn_wmd_support(E, ptr, ids, w, q, qw, 10.0, 4000)
+    prev = np.zeros(len(ptr) - 1)
+    for tol in (1e-2, 1e-4, 1e-6, 1e-9):
+        d, its = oracle.sinkhorn_wmd_support(E, ptr, ids, w, q, qw, 10.0, 4000, tol=tol)
+        assert np.all(its >= prev)
+        prev = its
+        # the count is the first iteration whose relative change of x is within tol
+        sel, r = oracle.select_query(E.shape[0], q, qw)
+        for k in range(len(ptr) - 1):
+            cw = w[ptr[k]:ptr[k + 1]] / w[ptr[k]:ptr[k + 1]].sum()
+            Md = cdist(E[sel], E[ids[ptr[k]:ptr[k + 1]]])
+            K = np.exp(-10.0 * Md)
+            x = np.ones(len(r)) / len(r)
+            first = None
+            for it in range(1, 4001):
+                xn = (K @ (cw / (K.T @ (1.0 / x)))) / r
+                if np.max(np.abs(xn - x) / xn) <= tol:
+                    first = it
+                    break
+                x = xn
+            assert first == its[k]
+    np.testing.assert_allclose(d, long_run, rtol=1e-7)
