@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--sweep", type=float, nargs="*", default=[], help="serving: extra arrival rates to try")
     ap.add_argument("--mem-budget-gb", type=float, default=24.0, help="serving: device memory for queries")
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each call's launches into a HIP graph once and replay it (on a side stream)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for HBM counters)")
     return ap.parse_args()
@@ -241,16 +243,20 @@ def main():
     itss = [torch.zeros((bt.B, c.N), dtype=torch.int32, device=dev) if args.tol > 0 else None for bt in batches]
     wss = [torch.empty(corpus.workspace_bytes(bt, args.schedule), dtype=torch.uint8, device=dev) for bt in batches]
 
+    # graphs replay on a stream of their own (capture needs one other than the legacy default)
+    run_stream = torch.cuda.Stream(device=dev) if args.graph else None
+
     def step():
         for bt, o, ws, its in zip(batches, outs, wss, itss):
             corpus.query(bt, w.lam, w.max_iter, cdist=args.cdist, schedule=args.schedule, out=o,
-                         workspace=ws, check=False, tol=args.tol, iters=its)
+                         workspace=ws, check=False, tol=args.tol, iters=its, stream=run_stream,
+                         graph=args.graph)
 
     # validity check of the configuration before timing
     step()
     torch.cuda.synchronize()
     for bt, ws in zip(batches, wss):
-        codes = corpus.query_errors(ws, bt.B)
+        codes = corpus.query_errors(ws, bt.B, run_stream)
         assert not codes.any(), codes
     for _ in range(args.warmup):
         step()
@@ -270,7 +276,8 @@ def main():
     value = docs_iters / (ms / 1e3)
     print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step", file=sys.stderr, flush=True)
 
-    # the same steps again with HIP events around every kernel launch
+    # the same steps again with HIP events around every kernel launch (eager:
+    # per-kernel timing bypasses graph replay)
     corpus.set_timing(True)
     t2 = time.perf_counter()
     for _ in range(args.steps):
@@ -318,7 +325,7 @@ def main():
         "vs_baseline": None, "dtype": "f32" if args.cdist == "fp32" else "bf16-gemm+f32",
         "data": "synthetic (seeded Zipf corpus and N(0,1/d) embeddings; no dataset)",
         "config": {"workload": describe(w, args.plain), "queries_per_step": Q.B, "docs": c.N,
-                   "max_iter": w.max_iter, "cdist": args.cdist, "schedule": args.schedule, "tol": args.tol,
+                   "max_iter": w.max_iter, "cdist": args.cdist, "schedule": args.schedule, "tol": args.tol, "graph": args.graph,
                    "compact_vocab": not args.no_compact, "vocab_rows_U": info["U"],
                    "tuned_shapes": corpus.pinned,
                    "parallelism": "single GPU"},

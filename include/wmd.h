@@ -50,9 +50,10 @@ typedef enum {
 typedef enum { WMD_CDIST_FP32 = 0, WMD_CDIST_BF16 = 1 } wmd_cdist;
 
 /* How the max_iter fused SDDMM-SpMM passes are scheduled.
- *  RESIDENT      one launch per (query, document-length bucket) runs every
- *                iteration and the final pass; each document's rows of K^T
- *                are gathered once and kept in registers.
+ *  RESIDENT      one launch per query (per document-length bucket where a
+ *                bucket needs several waves per document, see wmd_set_merge)
+ *                runs every iteration and the final pass; each document's
+ *                rows of K^T are gathered once and kept in registers.
  *  PER_ITERATION one launch per iteration (u round-trips through device
  *                memory, rows of K^T re-gathered each pass), as Section III-C
  *                runs one SDDMM_SpMM call per loop trip, then a final launch.
@@ -143,7 +144,16 @@ typedef struct {
                                  <= tol ("while x changes", Algorithm 1), and at
                                  max_iter at the latest.  Resident schedule only.       */
   int32_t* iters;             /* device, B*N int32 or NULL: iterations each document ran */
+  int32_t flags;              /* WMD_QUERY_* bits                                       */
 } wmd_query_desc;
+
+/* flags: capture the call's launch sequence into a HIP graph on first use and
+ * replay it when a later call on the same corpus has identical arguments
+ * (pointers, sizes, offsets, lambda, iterations, options).  Independent
+ * launch groups become parallel graph branches.  Needs a non-NULL stream;
+ * ignored while per-kernel timing is enabled.  A corpus keeps its 128 most
+ * recently used graphs. */
+#define WMD_QUERY_GRAPH 1
 
 /* Bytes of query workspace for B queries with these offsets and schedule
  * (0 on invalid input).  Dominated by K^T and (K.*M)^T: 8 * U * sum_b S_b bytes,
@@ -221,6 +231,19 @@ wmd_status wmd_sink_candidates(const wmd_corpus* c, int32_t S, int32_t cap, wmd_
  * table; NULL removes the pin.  A shape that cannot run (S, cap) is rejected
  * with WMD_ERR_INVALID_ARGUMENT. */
 wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_sink_shape* shape);
+
+/* How a query's length buckets are grouped into Sinkhorn launches.  Work
+ * items (query, document) are independent (Section III-C), so the grouping
+ * changes the time, and at most the float32 rounding of a bucket that runs
+ * with a different lane layout; each result stays deterministic.
+ *   WMD_MERGE_ALL:  every bucket whose documents one wave per item can hold
+ *                   (up to 16 rows per lane) joins one launch per query, the
+ *                   longest documents first (default)
+ *   WMD_MERGE_NONE: one launch per bucket
+ * Buckets with a pinned shape always launch on their own. */
+#define WMD_MERGE_ALL 0
+#define WMD_MERGE_NONE 1
+wmd_status wmd_set_merge(wmd_corpus* c, int32_t mode);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* wmd_last_error(void);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <list>
 #include <map>
 #include <cmath>
 #include <cstdio>
@@ -75,12 +76,23 @@ struct wmd_corpus {
   hipEvent_t join_ev[kSide] = {};
   std::mutex side_mu;  // one call at a time enqueues on the side streams
 
+  // captured launch sequences (WMD_QUERY_GRAPH), most recent first
+  struct GraphEntry { std::vector<uint64_t> key; hipGraph_t graph; hipGraphExec_t exec; };
+  std::list<GraphEntry> graphs;
+  int merge = WMD_MERGE_ALL;
+  std::mutex graph_mu;
+  static constexpr size_t kMaxGraphs = 128;
+
   // Sinkhorn shapes pinned per (padded query width, bucket capacity)
   std::map<std::pair<int, int>, SinkConfig> pinned;
   // tag of the next timed launch (query, S, cap, ndocs)
   int tag_query = -1, tag_S = 0, tag_cap = 0, tag_ndocs = 0;
 
   ~wmd_corpus() {
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     for (int i = 0; i < kSide; ++i) {
       if (side[i]) (void)hipStreamDestroy(side[i]);
@@ -303,9 +315,8 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
   return layout_for(c, plan, schedule).total;
 }
 
-wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace, size_t workspace_bytes,
-                     void* stream) {
-  g_err.clear();
+static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,
+                                size_t workspace_bytes, void* stream, bool in_graph) {
   if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
   if (!out || !workspace) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL output or workspace");
   if (!q->q_ptr || !q->q_ids || !q->q_weights) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL device query pointer");
@@ -372,77 +383,140 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
     WMD_HIP(launch_fill_i32(q->iters, n, schedule == WMD_SCHEDULE_RESIDENT ? 0 : q->max_iter, s));
   }
 
-  // a4-a6: Sinkhorn iterations and the final pass, per query and length bucket.
-  // Each (query, bucket) group is independent of the others; with more than
-  // one group they are spread over the side streams.
-  float* ubuf = at<float>(ws, L.u);
-  float* wbuf = at<float>(ws, L.w);
+  // a4-a6: Sinkhorn iterations and the final pass.  Per query, the length
+  // buckets that one-wave items hold share one launch; the others (and any
+  // bucket with a pinned shape) get launches of their own.  Launch units are
+  // independent of each other; with several they are spread over the side
+  // streams.
+  struct Unit {
+    bool merged = false;
+    MergePlan plan;
+    int off[kMergeMax] = {}, nd[kMergeMax] = {};
+    SinkConfig cfg{};
+    int bk = -1;
+    double nzb = 0.0, ndd = 0.0;
+    std::string name;
+  };
+  std::vector<std::vector<Unit>> units((size_t)q->B);
   int groups = 0;
-  for (int b = 0; b < q->B; ++b)
-    for (int bk = 0; bk < kNumBuckets; ++bk) groups += c->bucket_off[bk + 1] > c->bucket_off[bk];
-  const bool fork = groups > 3;
+  for (int b = 0; b < q->B; ++b) {
+    const int S = (int)plan.S[(size_t)b];
+    int caps[kNumBuckets], nds[kNumBuckets], bks[kNumBuckets], nm = 0;
+    for (int bk = 0; bk < kNumBuckets; ++bk) {
+      const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
+      if (nd == 0) continue;
+      if (c->pinned.count({S, kBucketCap[bk]})) continue;
+      caps[nm] = kBucketCap[bk]; nds[nm] = (int)nd; bks[nm] = bk; ++nm;
+    }
+    bool in_merge[kNumBuckets] = {};
+    MergePlan mp;
+    if (c->merge == WMD_MERGE_ALL && nm > 1 && plan_merge(S, caps, nds, nm, &mp) && mp.n > 1) {
+      Unit u;
+      u.merged = true;
+      u.plan = mp;
+      for (int g = 0; g < mp.n; ++g) {
+        const int bk = bks[mp.member[g]];
+        in_merge[bk] = true;
+        u.off[g] = (int)c->bucket_off[bk];
+        u.nd[g] = nds[mp.member[g]];
+        u.nzb += (double)c->bucket_nnz[bk];
+        u.ndd += (double)u.nd[g];
+      }
+      u.name = "sink_merge_kernel<" + std::to_string(mp.tc) + "," + std::to_string(mp.trmax) + "," +
+               std::to_string(mp.lg_cg) + ">x" + std::to_string(mp.n);
+      units[(size_t)b].push_back(std::move(u));
+    }
+    for (int bk = 0; bk < kNumBuckets; ++bk) {
+      const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
+      if (nd == 0 || in_merge[bk]) continue;
+      Unit u;
+      u.bk = bk;
+      auto pin = c->pinned.find({S, kBucketCap[bk]});
+      if (pin != c->pinned.end()) {
+        u.cfg = pin->second;
+      } else if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &u.cfg)) {
+        return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
+                                               " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
+      }
+      u.nzb = (double)c->bucket_nnz[bk];
+      u.ndd = (double)nd;
+      const SinkConfig& cfg = u.cfg;
+      u.name = cfg.stream ? std::string("sink_stream_kernel")
+                          : cfg.multiwave ? "sink_kernel<" + std::to_string(cfg.tc) + "," + std::to_string(cfg.tr) +
+                                                "," + std::to_string(cfg.lg_cg) + ">x" + std::to_string(cfg.nwaves)
+                                          : "sink_merge_kernel<" + std::to_string(cfg.tc) + "," +
+                                                std::to_string(cfg.tr) + "," + std::to_string(cfg.lg_cg) + ">x1";
+      units[(size_t)b].push_back(std::move(u));
+    }
+    groups += (int)units[(size_t)b].size();
+  }
+  // inside a graph, branches cost nothing on the host; eagerly, the event
+  // traffic only pays off with more groups
+  const bool fork = in_graph ? groups > 1 : groups > 3;
+  // side streams in use: every one that waits on the fork must be joined
+  // again (a stream left out of the join would end a capture unjoined)
+  const int nside = fork ? std::min(groups, wmd_corpus::kSide) : 0;
   std::unique_lock<std::mutex> side_lock(c->side_mu, std::defer_lock);
-  bool used_side[wmd_corpus::kSide] = {};
   if (fork) {
     side_lock.lock();
     WMD_HIP(hipEventRecord(c->fork_ev, s));
-    for (int i = 0; i < wmd_corpus::kSide; ++i) WMD_HIP(hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
+    for (int i = 0; i < nside; ++i) WMD_HIP(hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
   }
+  float* ubuf = at<float>(ws, L.u);
+  float* wbuf = at<float>(ws, L.w);
+  const int4* drec = at<int4>(c->ws, CL.drec);
   int group = 0;
   for (int b = 0; b < q->B; ++b) {
     const int64_t col0 = plan.col0[(size_t)b];
     const int S = (int)plan.S[(size_t)b];
     float* orow = out + (size_t)b * (size_t)c->N;
-    for (int bk = 0; bk < kNumBuckets; ++bk) {
-      const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
-      if (nd == 0) continue;
-      SinkConfig cfg{};
-      auto pin = c->pinned.find({S, kBucketCap[bk]});
-      if (pin != c->pinned.end()) {
-        cfg = pin->second;
-      } else if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &cfg)) {
-        return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
-                                               " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
-      }
-      c->tag_query = b; c->tag_S = S; c->tag_cap = kBucketCap[bk]; c->tag_ndocs = (int)nd;
-      SinkParams p{};
-      p.kt = kt + (size_t)col0 * (size_t)c->U;
-      p.r = sp.r + col0;
-      p.vr = sp.vr + b;
-      p.drec = at<int4>(c->ws, CL.drec) + c->bucket_off[bk];
-      p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);
-      p.ndocs = (int)nd;
-      p.S = S;
-      p.inv_lam = 1.0f / q->lambda;
-      p.tol = q->tol;
-      p.iters_out = (q->iters && schedule == WMD_SCHEDULE_RESIDENT) ? q->iters + (size_t)b * (size_t)c->N : nullptr;
-      p.out = orow;
-      p.u = ubuf + (size_t)col0 * (size_t)c->N;
-      p.w = wbuf + (size_t)b * (size_t)c->nnz;
-      const int grid = sink_grid(cfg, (int)nd);
-      const int si = group++ % wmd_corpus::kSide;
-      hipStream_t gs = fork ? c->side[si] : s;
-      used_side[si] = used_side[si] || fork;
+    SinkParams p{};
+    p.kt = kt + (size_t)col0 * (size_t)c->U;
+    p.r = sp.r + col0;
+    p.vr = sp.vr + b;
+    p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);
+    p.S = S;
+    p.inv_lam = 1.0f / q->lambda;
+    p.tol = q->tol;
+    p.iters_out = (q->iters && schedule == WMD_SCHEDULE_RESIDENT) ? q->iters + (size_t)b * (size_t)c->N : nullptr;
+    p.out = orow;
+    p.u = ubuf + (size_t)col0 * (size_t)c->N;
+    p.w = wbuf + (size_t)b * (size_t)c->nnz;
+    const double vrq = (double)(q->q_ptr_host[b + 1] - q->q_ptr_host[b]);
+    for (const Unit& u : units[(size_t)b]) {
+      hipStream_t gs = fork ? c->side[group % nside] : s;
+      ++group;
+      c->tag_query = b; c->tag_S = S;
+      c->tag_cap = u.merged ? 0 : kBucketCap[u.bk];
+      c->tag_ndocs = (int)u.ndd;
+      auto launch = [&](const SinkParams& a) -> hipError_t {
+        if (u.merged) {
+          SinkParams m = a;
+          m.drec = drec;
+          int grid = 0;
+          return launch_sink_merged(m, u.plan, u.off, u.nd, gs, &grid);
+        }
+        SinkParams one = a;
+        one.drec = drec + c->bucket_off[u.bk];
+        one.ndocs = (int)u.ndd;
+        return launch_sink(one, u.cfg, sink_grid(u.cfg, one.ndocs), gs);
+      };
       // algorithmic work per document and iteration (n_k entries, v_r query words):
       // 4 v_r n_k + n_k + 2 v_r flops; 8 n_k + 4 v_r n_k + 8 v_r bytes when u and the
       // K^T rows travel through memory every pass.  The final pass does
       // 4 v_r n_k + 2 n_k flops.
-      const double vrq = (double)(q->q_ptr_host[b + 1] - q->q_ptr_host[b]);
-      const double nzb = (double)c->bucket_nnz[bk], ndd = (double)nd;
+      const double nzb = u.nzb, ndd = u.ndd;
       const double it_flops = 4.0 * vrq * nzb + nzb + 2.0 * vrq * ndd;
       const double it_bytes = 8.0 * nzb + 4.0 * vrq * nzb + 8.0 * vrq * ndd;
       const double fin_flops = 4.0 * vrq * nzb + 2.0 * nzb;
-      const std::string name = cfg.stream ? std::string("sink_stream_kernel")
-                                          : "sink_kernel<" + std::to_string(cfg.tc) + "," + std::to_string(cfg.tr) +
-                                                "," + std::to_string(cfg.lg_cg) + "," +
-                                                (cfg.multiwave ? "true>x" + std::to_string(cfg.nwaves) : "false>");
       auto go = [&](const SinkParams& a, double fl, double by) {
-        return timed_launch(c, gs, name, fl, by, [&] { return launch_sink(a, cfg, grid, gs); });
+        return timed_launch(c, gs, u.name, fl, by, [&] { return launch(a); });
       };
       if (schedule == WMD_SCHEDULE_RESIDENT) {
-        p.iters = q->max_iter; p.do_final = 1;
+        SinkParams a = p;
+        a.iters = q->max_iter; a.do_final = 1;
         // resident: the entries, the document records and the K^T rows are read once
-        WMD_HIP(go(p, q->max_iter * it_flops + fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 20.0 * ndd));
+        WMD_HIP(go(a, q->max_iter * it_flops + fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 20.0 * ndd));
       } else {
         for (int it = 0; it < q->max_iter; ++it) {
           if (schedule == WMD_SCHEDULE_PER_ITERATION) {
@@ -463,17 +537,24 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
         WMD_HIP(go(f, fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd + 20.0 * ndd));
       }
     }
-      c->tag_query = b; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = (int)c->empty_count;
+    c->tag_query = b; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = (int)c->empty_count;
     if (c->empty_count > 0)
       WMD_HIP(timed_launch(c, s, "nan_docs_kernel", 0.0, 8.0 * c->empty_count,
                            [&] { return launch_nan_docs(c->docs() + c->empty_off, c->empty_count, orow, s); }));
   }
   if (fork)
-    for (int i = 0; i < wmd_corpus::kSide; ++i) {
-      if (!used_side[i]) continue;
+    for (int i = 0; i < nside; ++i) {
       WMD_HIP(hipEventRecord(c->join_ev[i], c->side[i]));
       WMD_HIP(hipStreamWaitEvent(s, c->join_ev[i], 0));
     }
+  return WMD_OK;
+}
+
+wmd_status wmd_set_merge(wmd_corpus* c, int32_t mode) {
+  g_err.clear();
+  if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
+  if (mode != WMD_MERGE_ALL && mode != WMD_MERGE_NONE) return fail(WMD_ERR_INVALID_ARGUMENT, "unknown merge mode");
+  c->merge = mode;
   return WMD_OK;
 }
 
@@ -510,6 +591,68 @@ wmd_status wmd_get_timing(wmd_corpus* c, wmd_kernel_stat* stats, int32_t capacit
   const int32_t n = (int32_t)acc.size();
   for (int32_t i = 0; i < n && i < capacity; ++i) stats[i] = acc[(size_t)i];
   *count = n;
+  return WMD_OK;
+}
+
+static uint64_t bits_of(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+  g_err.clear();
+  if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
+  const bool graph = (q->flags & WMD_QUERY_GRAPH) && stream != nullptr && !c->timing;
+  if (!graph) return enqueue_query(c, q, out, workspace, workspace_bytes, stream, false);
+  if (q->B < 1 || !q->q_ptr_host) return fail(WMD_ERR_INVALID_ARGUMENT, "B must be >= 1 with host offsets");
+  // every argument the captured launches depend on
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)workspace, (uint64_t)workspace_bytes,
+                               (uint64_t)(uintptr_t)q->q_ptr, (uint64_t)(uintptr_t)q->q_ids,
+                               (uint64_t)(uintptr_t)q->q_weights, (uint64_t)(uintptr_t)q->iters,
+                               (uint64_t)q->B, bits_of(q->lambda), (uint64_t)q->max_iter, (uint64_t)q->cdist,
+                               (uint64_t)q->schedule, bits_of(q->tol)};
+  key.push_back((uint64_t)c->merge);
+  for (int b = 0; b <= q->B; ++b) key.push_back((uint64_t)q->q_ptr_host[b]);
+  for (const auto& p : c->pinned) {
+    key.push_back(((uint64_t)p.first.first << 32) | (uint32_t)p.first.second);
+    key.push_back(((uint64_t)p.second.tc << 48) | ((uint64_t)p.second.tr << 32) | ((uint64_t)p.second.lg_cg << 16) |
+                  ((uint64_t)p.second.nwaves << 4) | (uint64_t)p.second.maxw);
+  }
+  int dev = 0;
+  WMD_HIP(hipGetDevice(&dev));
+  if (dev != c->device) return fail(WMD_ERR_INVALID_ARGUMENT, "current device differs from the corpus device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> graph_lock(c->graph_mu);
+  for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
+    if (it->key != key) continue;
+    c->graphs.splice(c->graphs.begin(), c->graphs, it);  // most recent first
+    WMD_HIP(hipGraphLaunch(c->graphs.front().exec, s));
+    return WMD_OK;
+  }
+  WMD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  wmd_status st = enqueue_query(c, q, out, workspace, workspace_bytes, stream, true);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != WMD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(WMD_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(WMD_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  c->graphs.push_front({std::move(key), g, x});
+  if (c->graphs.size() > wmd_corpus::kMaxGraphs) {
+    (void)hipGraphExecDestroy(c->graphs.back().exec);
+    (void)hipGraphDestroy(c->graphs.back().graph);
+    c->graphs.pop_back();
+  }
+  WMD_HIP(hipGraphLaunch(x, s));
   return WMD_OK;
 }
 

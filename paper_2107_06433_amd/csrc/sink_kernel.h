@@ -118,8 +118,10 @@ __device__ __forceinline__ int64_t rec_begin(const int4& r) {
   return (int64_t)(uint32_t)r.x | ((int64_t)r.y << 32);
 }
 
+// One launch group's share of the work: block `blk` of `nblk` blocks walks
+// the items blk, blk + nblk, ... of p's documents.
 template <int TC, int TR, int LG_CG, int MAXW>
-__global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParams p) {
+__device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk) {
   constexpr bool MW = MAXW > 1;                   // an item spans several waves of one block
   constexpr int CG = 1 << LG_CG;
   constexpr int RSW = 64 >> LG_CG;                // row lanes per wave
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParam
   const int S = p.S;
   const int vr = *p.vr;
 
-  for (int base = blockIdx.x * items; base < p.ndocs; base += gridDim.x * items) {
+  for (int base = blk * items; base < p.ndocs; base += nblk * items) {
     const int item = base + slot;
     const bool active = item < p.ndocs;
     const int4 rec = active ? p.drec[item] : make_int4(0, 0, 0, 0);
@@ -333,12 +335,55 @@ __global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParam
   }
 }
 
-using SinkFn = void (*)(SinkParams);
+// Multi-wave items: one item per block of up to MAXW waves.
+template <int TC, int TR, int LG_CG, int MAXW>
+__global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParams p) {
+  sink_body<TC, TR, LG_CG, MAXW>(p, blockIdx.x, gridDim.x);
+}
+
+// One-wave items, four per block, for several length buckets of one query in
+// a single launch.  Group g holds blocks [end[g-1], end[g]) and documents
+// drec[off[g]] ... drec[off[g] + ndocs[g] - 1]; its rows per lane are TRMAX
+// (body 0), TRMAX/2 (body 1) or TRMAX/4 (body 2), enough for its bucket.
+// Groups come longest documents first, so the longest items start first and
+// the short ones fill in behind them.  The other fields of p are shared.
+template <int TC, int TRMAX, int LG_CG>
+__global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
+  const int b = blockIdx.x;
+  int g = 0, b0 = 0;
+#pragma unroll
+  for (int i = 0; i + 1 < kMergeMax; ++i)
+    if (i + 1 < m.ngroups && b >= m.end[i]) {
+      g = i + 1;
+      b0 = m.end[i];
+    }
+  int off = 0, nd = 0, body = 0, b1 = 0;
+#pragma unroll
+  for (int i = 0; i < kMergeMax; ++i)
+    if (i == g) {
+      off = m.off[i];
+      nd = m.ndocs[i];
+      body = m.body[i];
+      b1 = m.end[i];
+    }
+  SinkParams p = m.p;
+  p.drec += off;
+  p.ndocs = nd;
+  if (body == 0) {
+    sink_body<TC, TRMAX, LG_CG, 1>(p, b - b0, b1 - b0);
+  } else if constexpr (TRMAX >= 2) {
+    if (body == 1) {
+      sink_body<TC, TRMAX / 2, LG_CG, 1>(p, b - b0, b1 - b0);
+    } else if constexpr (TRMAX >= 4) {
+      sink_body<TC, TRMAX / 4, LG_CG, 1>(p, b - b0, b1 - b0);
+    }
+  }
+}
 
 struct SinkEntry {
   int tc, tr, lg_cg;
-  int maxw;   // 1: one wave per item; 4 or 16: waves per block at most
-  SinkFn fn;
+  int maxw;       // 1: one wave per item (sink_merge_kernel, TRMAX = tr); 4 or 16: waves per block at most
+  const void* fn;
 };
 
 // Register budget per lane of the K^T block: up to 128 cells with at most 4
@@ -357,7 +402,12 @@ struct SinkPick {
 };
 template <int TC, int TR, int LG_CG, int MAXW>
 struct SinkPick<TC, TR, LG_CG, MAXW, true> {
-  static SinkEntry get() { return SinkEntry{TC, TR, LG_CG, MAXW, (SinkFn)sink_kernel<TC, TR, LG_CG, MAXW>}; }
+  static SinkEntry get() {
+    if constexpr (MAXW == 1)
+      return SinkEntry{TC, TR, LG_CG, MAXW, (const void*)sink_merge_kernel<TC, TR, LG_CG>};
+    else
+      return SinkEntry{TC, TR, LG_CG, MAXW, (const void*)sink_kernel<TC, TR, LG_CG, MAXW>};
+  }
 };
 
 #define WMD_SINK_ENTRY(TC, TR, LG, MAXW) SinkPick<TC, TR, LG, MAXW>::get(),

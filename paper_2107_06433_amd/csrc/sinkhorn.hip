@@ -134,7 +134,7 @@ const std::vector<Shape>& shapes() {
         hipFuncAttributes a{};
         int regs = 128;
         bool spills = false;
-        if (hipFuncGetAttributes(&a, (const void*)t[i].fn) == hipSuccess) {
+        if (hipFuncGetAttributes(&a, t[i].fn) == hipSuccess) {
           if (a.numRegs > 0) regs = a.numRegs;
           spills = a.localSizeBytes > 0;
         }
@@ -269,8 +269,136 @@ hipError_t launch_sink(const SinkParams& p, const SinkConfig& c, int grid, hipSt
   }
   const Shape* sh = find_shape(c);
   if (!sh) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sh->e.fn, dim3(grid), dim3(sink_block(c)), lds_bytes(c), s, p);
-  return hipGetLastError();
+  if (sh->e.maxw == 1) {  // a merged launch with a single group
+    SinkMerge m{};
+    m.p = p;
+    m.ngroups = 1;
+    m.end[0] = grid;
+    m.ndocs[0] = p.ndocs;
+    void* args[] = {&m};
+    return hipLaunchKernel(sh->e.fn, dim3(grid), dim3(256), args, 0, s);
+  }
+  SinkParams a = p;
+  void* args[] = {&a};
+  return hipLaunchKernel(sh->e.fn, dim3(grid), dim3(sink_block(c)), args, lds_bytes(c), s);
+}
+
+namespace {
+
+// Rows per lane a one-wave item of 2^lg_cg column lanes needs for `cap` words.
+int tr_needed(int lg_cg, int cap) {
+  const int rsw = 64 >> lg_cg;
+  int tr = 1;
+  while (rsw * tr < cap) tr *= 2;
+  return tr;
+}
+
+double merged_cost(const Shape& variant, const int* tr, const int* nd, int n) {
+  const SinkEntry& e = variant.e;
+  const int regs = (variant.regs + 7) & ~7;
+  int occ = 512 / regs;
+  occ = occ > 8 ? 8 : occ;
+  double issue = 0.0, imax = 0.0, waves = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double I = 2.0 * tr[i] * e.tc + tr[i] * e.lg_cg + e.tc * (6 - e.lg_cg) + 2.0 * tr[i] + 2.0 * e.tc;
+    issue += (double)nd[i] * I * 4.0 / 1024.0;
+    imax = I > imax ? I : imax;
+    waves += nd[i];
+  }
+  const double lat = std::ceil(waves / (1024.0 * occ)) * imax * 8.0;
+  return issue > lat ? issue : lat;
+}
+
+}  // namespace
+
+// One launch for the buckets of one query that one-wave items can hold.  A
+// candidate is a compiled one-wave shape (tc, TRMAX, lg_cg) whose columns
+// cover S with the fewest padded columns: the buckets needing at most TRMAX
+// rows per lane join (at least one needing exactly TRMAX), each with the
+// smallest of TRMAX, TRMAX/2, TRMAX/4 that holds it; the others keep launches
+// of their own.  The candidate holding the most buckets wins, the lowest
+// modelled time (the separate launches included) among equals.  Measured on
+// single queries, one launch over every bucket beat splitting them even where
+// the model preferred a split: the short items fill in behind the long ones.
+bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out) {
+  double best = 0.0;
+  bool found = false;
+  std::vector<double> alone((size_t)nb, -1.0);
+  for (const Shape& sh : shapes()) {
+    const SinkEntry& e = sh.e;
+    if (e.maxw != 1 || sh.spills) continue;
+    const int CG = 1 << e.lg_cg;
+    if (e.tc * CG < S || (e.tc - 1) * CG >= S) continue;
+    MergePlan p{};
+    p.tc = e.tc; p.trmax = e.tr; p.lg_cg = e.lg_cg;
+    int trs[kMergeMax], nds[kMergeMax];
+    bool exact = false;
+    double rest = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      const int t = tr_needed(e.lg_cg, cap[i]);
+      if (t > e.tr || p.n == kMergeMax) {
+        if (alone[(size_t)i] < 0.0) {
+          alone[(size_t)i] = 1e30;
+          for (const Shape& o : shapes()) {
+            if (o.spills) continue;
+            const int nw = waves_for(o.e, S, cap[i]);
+            if (!nw) continue;
+            SinkConfig oc{o.e.tc, o.e.tr, o.e.lg_cg, nw, o.e.maxw > 1, false, o.e.maxw};
+            if (lds_bytes(oc) > 65536) continue;
+            alone[(size_t)i] = std::min(alone[(size_t)i], model_cost(o, nw, ndocs[i]));
+          }
+        }
+        rest += alone[(size_t)i];
+        continue;
+      }
+      exact = exact || t == e.tr;
+      int body = 0;
+      while (body < 2 && (e.tr >> (body + 1)) >= t) ++body;
+      p.member[p.n] = i;
+      p.body[p.n] = body;
+      trs[p.n] = e.tr >> body;
+      nds[p.n] = ndocs[i];
+      ++p.n;
+    }
+    if (p.n == 0 || !exact) continue;
+    const double c = merged_cost(sh, trs, nds, p.n) + rest;
+    if (!found || p.n > out->n || (p.n == out->n && c < best)) {
+      best = c;
+      *out = p;
+      found = true;
+    }
+  }
+  if (!found) return false;
+  // longest documents first
+  MergePlan& p = *out;
+  for (int i = 1; i < p.n; ++i)
+    for (int j = i; j > 0 && cap[p.member[j]] > cap[p.member[j - 1]]; --j) {
+      std::swap(p.member[j], p.member[j - 1]);
+      std::swap(p.body[j], p.body[j - 1]);
+    }
+  return true;
+}
+
+hipError_t launch_sink_merged(const SinkParams& p, const MergePlan& plan, const int* off, const int* ndocs,
+                              hipStream_t s, int* grid_out) {
+  SinkConfig c{plan.tc, plan.trmax, plan.lg_cg, 1, false, false, 1};
+  const Shape* sh = find_shape(c);
+  if (!sh || plan.n < 1 || plan.n > kMergeMax) return hipErrorInvalidValue;
+  SinkMerge m{};
+  m.p = p;
+  m.ngroups = plan.n;
+  int grid = 0;
+  for (int g = 0; g < plan.n; ++g) {
+    grid += (ndocs[g] + 3) / 4;
+    m.end[g] = grid;
+    m.off[g] = off[g];
+    m.ndocs[g] = ndocs[g];
+    m.body[g] = plan.body[g];
+  }
+  *grid_out = grid;
+  if (grid == 0) return hipSuccess;
+  void* args[] = {&m};
+  return hipLaunchKernel(sh->e.fn, dim3(grid), dim3(256), args, 0, s);
 }
 
 }  // namespace wmd

@@ -107,6 +107,18 @@ struct SinkParams {
   int* iters_out;         // per document of this query (indexed by id), or null
 };
 
+// Several length buckets of one query in one launch of one-wave items
+// (groups longest documents first; see sink_merge_kernel).
+constexpr int kMergeMax = 8;
+struct SinkMerge {
+  SinkParams p;           // drec and ndocs are replaced per group
+  int ngroups;
+  int end[kMergeMax];     // one past the group's last block
+  int off[kMergeMax];     // the group's first document record
+  int ndocs[kMergeMax];
+  int body[kMergeMax];    // rows per lane TRMAX >> body
+};
+
 // Register-resident shape: tc x tr cells per lane, 2^lg_cg column lanes, an item
 // spans `nwaves` waves of one block when multiwave (maxw = 4 or 16: the block
 // size the kernel was compiled for), else one wave with four items per block.
@@ -143,5 +155,19 @@ bool sink_config_supported(const SinkConfig& cfg);
 bool sink_config_fits(const SinkConfig& cfg, int S, int cap);
 int sink_grid(const SinkConfig& cfg, int ndocs);
 int sink_block(const SinkConfig& cfg);
+
+// One launch over several length buckets of one query (one-wave items).
+// member[g] indexes the caller's bucket list, longest documents first; group g
+// runs with trmax >> body[g] rows per lane.
+struct MergePlan {
+  int tc = 0, trmax = 0, lg_cg = 0;
+  int n = 0;
+  int member[kMergeMax] = {};
+  int body[kMergeMax] = {};
+};
+bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out);
+// off / ndocs: per group, in plan order; p.drec is the start of all records.
+hipError_t launch_sink_merged(const SinkParams& p, const MergePlan& plan, const int* off, const int* ndocs,
+                              hipStream_t s, int* grid_out);
 
 }  // namespace wmd

@@ -22,14 +22,16 @@ WMD_OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "device error", 4: "not supported"}
 CDIST = {"fp32": 0, "bf16": 1}
 SCHEDULE = {"auto": 0, "resident": 1, "per_iteration": 2, "unfused": 3}
+QUERY_GRAPH = 1
 QUERY_ERRORS = {0: "ok", 1: "query word id out of range", 2: "query weight negative or not finite",
                 3: "query has no positive weight", 4: "query too long"}
 
 EXPORTS = [
     "wmd_corpus_workspace_bytes", "wmd_create_corpus", "wmd_get_corpus_info", "wmd_destroy",
     "wmd_query_workspace_bytes", "wmd_query", "wmd_query_errors", "wmd_set_timing", "wmd_get_timing",
-    "wmd_get_launches", "wmd_sink_candidates", "wmd_set_sink_shape", "wmd_last_error",
+    "wmd_get_launches", "wmd_sink_candidates", "wmd_set_sink_shape", "wmd_set_merge", "wmd_last_error",
 ]
+MERGE = {"all": 0, "none": 1}
 TUNING_FILE = os.path.join(_PKG, "tuning", "gfx950_sink_shapes.json")
 
 
@@ -57,7 +59,7 @@ class QueryDesc(ctypes.Structure):
         ("B", ctypes.c_int32), ("q_ptr_host", ctypes.c_void_p), ("q_ptr", ctypes.c_void_p),
         ("q_ids", ctypes.c_void_p), ("q_weights", ctypes.c_void_p), ("lam", ctypes.c_float),
         ("max_iter", ctypes.c_int32), ("cdist", ctypes.c_int32), ("schedule", ctypes.c_int32),
-        ("tol", ctypes.c_float), ("iters", ctypes.c_void_p),
+        ("tol", ctypes.c_float), ("iters", ctypes.c_void_p), ("flags", ctypes.c_int32),
     ]
 
 
@@ -111,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wmd_sink_candidates.restype = i32
     lib.wmd_set_sink_shape.argtypes = [vp, i32, i32, ctypes.POINTER(SinkShape)]
     lib.wmd_set_sink_shape.restype = i32
+    lib.wmd_set_merge.argtypes = [vp, i32]
+    lib.wmd_set_merge.restype = i32
     lib.wmd_last_error.argtypes = []
     lib.wmd_last_error.restype = ctypes.c_char_p
     return lib
@@ -232,6 +236,10 @@ class Corpus:
         else:
             _check(lib().wmd_set_sink_shape(self._h, S, cap, ctypes.byref(SinkShape(**shape))))
 
+    def set_merge(self, mode: str) -> None:
+        """How length buckets share Sinkhorn launches: "all" (default) or "none"."""
+        _check(lib().wmd_set_merge(self._h, MERGE[mode]))
+
     def load_tuning(self, path: str) -> int:
         """Pin shapes from a measured tuning table; returns how many were applied.
 
@@ -305,11 +313,18 @@ class Corpus:
     def query(self, batch: QueryBatch, lam: float, max_iter: int, cdist: str = "fp32",
               schedule: str = "auto", out: torch.Tensor | None = None,
               workspace: torch.Tensor | None = None, stream=None, check: bool = True,
-              tol: float = 0.0, iters: torch.Tensor | None = None) -> torch.Tensor:
+              tol: float = 0.0, iters: torch.Tensor | None = None, graph: bool = False) -> torch.Tensor:
         """Distances of every query to every document: float32 [B, N] on the device.
 
         With ``check`` the call waits for the stream and raises ValueError if a
         query held an invalid id or weight (its row is NaN either way).
+
+        With ``graph`` the launch sequence is captured into a HIP graph the
+        first time and replayed by later calls whose arguments are identical
+        (same out / workspace / query tensors and offsets, lambda, iterations,
+        options); the device contents of the query tensors may change between
+        calls.  Pass ``out`` and ``workspace`` to reuse a graph.  Needs a
+        stream other than the legacy default stream.
         """
         B = batch.B
         if out is None:
@@ -322,7 +337,7 @@ class Corpus:
         desc = QueryDesc(B=B, q_ptr_host=batch.q_ptr_host.ctypes.data, q_ptr=_ptr(batch.q_ptr),
                          q_ids=_ptr(batch.ids), q_weights=_ptr(batch.weights), lam=float(lam),
                          max_iter=int(max_iter), cdist=CDIST[cdist], schedule=SCHEDULE[schedule],
-                         tol=float(tol), iters=_ptr(iters))
+                         tol=float(tol), iters=_ptr(iters), flags=QUERY_GRAPH if graph else 0)
         sh = _stream_handle(stream)
         with torch.cuda.device(self.device):
             _check(lib().wmd_query(self._h, ctypes.byref(desc), _ptr(out), _ptr(workspace),

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 def test_ctypes_structs_match_header_layout():
     # sizes implied by the C declarations on LP64
     assert ctypes.sizeof(wmd.CorpusDesc) == 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(wmd.QueryDesc) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 8
+    assert ctypes.sizeof(wmd.QueryDesc) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(wmd.CorpusInfo) == 3 * 8 + 2 * 4 + 8 + 8 + 8 + 16 * 8 + 16 * 4
 
 

@@ -197,6 +197,44 @@ def test_batch_invariance(W, batched):
         assert np.array_equal(alone, full[b]), f"query {b} differs alone vs in the batch"
 
 
+def test_graph_replays_match_eager(W, batched):
+    """Captured launches replay bit-identically to eager calls, with eager
+    work (a fill of the output, another query on another stream) between the
+    replays; new query contents written in place are picked up by a replay."""
+    corpus = corpus_of(W, batched.corpus)
+    Q, N, lam, it = batched.queries, batched.corpus.N, batched.lam, batched.max_iter
+    batch = W.QueryBatch.from_arrays(Q.q_ptr, Q.ids, Q.weights)
+    other = W.QueryBatch.from_arrays(Q.q_ptr[:6], Q.ids[:Q.q_ptr[5]], Q.weights[:Q.q_ptr[5]])
+    s = torch.cuda.Stream()
+    for tol in (0.0, 1e-3):
+        ref_it = torch.zeros(Q.B * N, dtype=torch.int32, device="cuda")
+        ref = corpus.query(batch, lam, it, tol=tol, iters=ref_it, stream=s).cpu().numpy()
+        out = torch.empty((Q.B, N), dtype=torch.float32, device="cuda")
+        ws = torch.empty(corpus.workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+        g_it = torch.zeros(Q.B * N, dtype=torch.int32, device="cuda")
+        for rep in range(4):
+            with torch.cuda.stream(s):
+                out.fill_(float("nan"))
+                g_it.fill_(-1)
+            corpus.query(batch, lam, it, tol=tol, iters=g_it, out=out, workspace=ws, stream=s, graph=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), ref, err_msg=f"tol={tol} replay {rep}")
+            assert torch.equal(g_it, ref_it), f"tol={tol} replay {rep}: iteration counts differ"
+            corpus.query(other, lam, it)  # eager work between replays
+            torch.cuda.synchronize()
+    # same tensors, new contents: the replay reads them at run time
+    ids2 = ((Q.ids.astype(np.int64) + 1) % batched.corpus.emb.shape[0]).astype(np.int32)
+    ref2_it = torch.zeros_like(g_it)
+    ref2 = corpus.query(W.QueryBatch.from_arrays(Q.q_ptr, ids2, Q.weights), lam, it, tol=1e-3,
+                        iters=ref2_it).cpu().numpy()
+    batch.ids.copy_(torch.from_numpy(ids2))
+    torch.cuda.synchronize()
+    corpus.query(batch, lam, it, tol=1e-3, iters=g_it, out=out, workspace=ws, stream=s, graph=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref2)
+    assert torch.equal(g_it, ref2_it)
+
+
 # ----------------------------------------------------------------- edge cases
 
 def handmade_corpus(rng, V, d, lengths, dup=False):
@@ -248,6 +286,34 @@ def test_all_length_buckets_and_multiwave_items(W):
         ids, qw = q.query(b)
         ref = oracle_support(c, ids, qw, 10.0, 15)
         assert_close(got[b], ref, TOL32, f"query width {len(ids)}")
+
+
+def test_merged_launches_match_separate_launches(W):
+    """One launch over several length buckets computes what one launch per
+    bucket computes.  A short bucket may run with more rows per lane in the
+    shared launch (or another column layout), which reorders its float32 sums,
+    so the two agree to rounding rather than bit for bit; both match the
+    oracle on sampled documents."""
+    rng = np.random.default_rng(44)
+    lengths = np.concatenate([rng.integers(1, 300, size=700), rng.integers(300, 1100, size=40), [0, 0]])
+    rng.shuffle(lengths)
+    c = handmade_corpus(rng, 5000, 40, lengths)
+    qs = [rng.choice(5000, size=v, replace=False) for v in (1, 7, 20, 33, 64, 130)]
+    q = synth.Queries(q_ptr=np.concatenate([[0], np.cumsum([len(x) for x in qs])]),
+                      ids=np.concatenate(qs).astype(np.int32),
+                      weights=rng.integers(1, 4, size=sum(len(x) for x in qs)).astype(np.float32))
+    corpus = corpus_of(W, c)
+    merged = run(W, corpus, q, 10.0, 15)
+    corpus.set_merge("none")
+    separate = run(W, corpus, q, 10.0, 15)
+    assert_close(merged, separate, 1e-5, "merged vs separate launches")
+    with pytest.raises(W.WMDError):  # an unknown mode is rejected
+        W._check(W.lib().wmd_set_merge(corpus._h, 7))
+    docs = np.sort(rng.choice(len(lengths), size=40, replace=False))
+    for b in range(q.B):
+        ids, qw = q.query(b)
+        ref = oracle_support(c, ids, qw, 10.0, 15, docs)
+        assert_close(merged[b, docs], ref, TOL32, f"merged, query width {len(ids)}")
 
 
 @pytest.mark.parametrize("vr", [1, 3, 4, 5, 63, 64, 65, 500, 2048])
