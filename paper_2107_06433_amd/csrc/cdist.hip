@@ -187,10 +187,10 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
 // Few query columns (C <= 32): the GEMM is a stream over the U x dp vocabulary
 // rows.  Each wave owns 16 rows and reads them straight from memory into the
 // MFMA operand registers -- for every 16 (f32) or 32 (bf16) k values, the four
-// lane quads of a row read one contiguous 64-byte piece.  All loads of a row
-// (up to 24 steps) are issued at once, before Q (at most 32 rows) is staged in
-// LDS and before the epilogue's per-row data is fetched, so one memory latency
-// covers the whole row.
+// lane quads of a row read one contiguous 64-byte piece.  Q (at most 32 rows)
+// is staged in LDS first; then all loads of a row (up to 24 steps) are issued
+// at once, before the epilogue's per-row data is fetched, so one memory
+// latency covers the whole row.
 template <int NT, bool BF16>
 __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   constexpr int ESZ = BF16 ? 2 : 4;
@@ -210,13 +210,36 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // Q: NT*16 rows (zero beyond C) go to LDS first, eight 16-byte pieces per
+  // thread in flight at a time (one L2 round trip for typical widths), before
+  // any vocabulary load: loads complete in order, so Q pieces issued behind the
+  // vocabulary row would wait for all of it.
+  const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
+  const int vpr = dp * ESZ / 16;
+  const int qtotal = NT * 16 * vpr;
+  for (int i0 = 0; i0 < qtotal; i0 += 8 * 256) {
+    uint4 qv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = i0 + j * 256 + tid;
+      const int row = i / vpr;
+      qv[j] = (i < qtotal && row < p.C) ? *(const uint4*)(Qg + (size_t)row * row_bytes + 16 * (i - row * vpr))
+                                        : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = i0 + j * 256 + tid;
+      const int row = i / vpr;
+      if (i < qtotal) *(uint4*)(smem + row * ldq + 16 * (i - row * vpr)) = qv[j];
+    }
+  }
   uint4 buf[CH];
   auto load = [&](int s0) {
 #pragma unroll
     for (int i = 0; i < CH; ++i)
       buf[i] = (row_ok && s0 + i < nsteps) ? *(const uint4*)(Ag + (size_t)(s0 + i) * 64) : make_uint4(0, 0, 0, 0);
   };
-  load(0);  // the first vocabulary loads are in flight while Q is staged
+  load(0);
   // the epilogue's per-row data, fetched early for the same reason
   float en_r[4];
   int used_r[4];
@@ -225,15 +248,6 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     const int64_t m = m0 + 4 * (lane >> 4) + i;
     en_r[i] = m < p.U ? p.en[m] : 0.f;
     used_r[i] = m < p.U ? p.used[m] : -1;
-  }
-  // stage Q: NT*16 rows (zero beyond C)
-  const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
-  const int vpr = dp * ESZ / 16;
-  for (int i = tid; i < NT * 16 * vpr; i += 256) {
-    const int row = i / vpr, v = i % vpr;
-    uint4 x = make_uint4(0, 0, 0, 0);
-    if (row < p.C) x = *(const uint4*)(Qg + (size_t)row * row_bytes + 16 * v);
-    *(uint4*)(smem + row * ldq + 16 * v) = x;
   }
   __syncthreads();
   for (int s0 = 0; s0 < nsteps; s0 += CH) {

@@ -53,6 +53,36 @@ __device__ __forceinline__ float add_xor32(float x) {
   return __uint_as_float(p[0]) + __uint_as_float(p[1]);
 }
 
+// Reduce-scatter and gather over the permlane bits.  Lane bit 4 selects the
+// 16-lane group inside a half wave, bit 5 the half.  permlane16_swap(x, y)
+// returns x with its odd groups replaced by y's even groups and y with its
+// even groups replaced by x's odd groups, so the sum of the two results holds
+// x summed over bit 4 in the even groups and y summed over bit 4 in the odd
+// ones; permlane32_swap does the same for the halves.
+
+// [a + a^16 in groups 0 and 2, b + b^16 in groups 1 and 3]
+__device__ __forceinline__ float sum_scatter16(float a, float b) {
+  auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+// [a + a^32 in lanes 0-31, b + b^32 in lanes 32-63]
+__device__ __forceinline__ float sum_scatter32(float a, float b) {
+  auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+// inverse of the scatters: v holds a in even groups (lower half) and b in odd
+// groups (upper half); every lane receives both
+__device__ __forceinline__ void gather16(float v, float& a, float& b) {
+  auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  a = __uint_as_float(p[0]);
+  b = __uint_as_float(p[1]);
+}
+__device__ __forceinline__ void gather32(float v, float& a, float& b) {
+  auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  a = __uint_as_float(p[0]);
+  b = __uint_as_float(p[1]);
+}
+
 // Sum over lane bits [0, nbits), every lane of the group receiving the total.
 // Lower bits are summed first, so once bits 0..b-1 are uniform the mirror
 // patterns (which flip several bits at once) pair lanes that hold equal

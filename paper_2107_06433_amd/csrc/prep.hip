@@ -186,7 +186,30 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
     const int q = i >= 0 ? s_id[i] : -1;
     const float* src = p.emb + (size_t)(q < 0 ? 0 : q) * p.d;
     double nrm = 0.0;
-    if (s < S) {
+    if (s < S && (p.d & 3) == 0 && ((uintptr_t)p.emb & 15) == 0 && p.dp <= 512) {
+      // rows of 16-byte pieces: piece lane8 + 8 i of the row for i < 16, every
+      // load of the row issued before the first store
+      float4 x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int k = 4 * (lane8 + 8 * i);
+        x[i] = (q >= 0 && k < p.d) ? *(const float4*)(src + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int k = 4 * (lane8 + 8 * i);
+        if (k < p.dp) {
+          *(float4*)(p.q32 + (size_t)(col0 + s) * p.dp + k) = x[i];
+          if (p.want_bf16) {
+            const uint32_t lo = (uint32_t)f32_to_bf16(x[i].x) | ((uint32_t)f32_to_bf16(x[i].y) << 16);
+            const uint32_t hi = (uint32_t)f32_to_bf16(x[i].z) | ((uint32_t)f32_to_bf16(x[i].w) << 16);
+            *(uint2*)(p.q16 + (size_t)(col0 + s) * p.dp + k) = make_uint2(lo, hi);
+          }
+          nrm += (double)x[i].x * (double)x[i].x + (double)x[i].y * (double)x[i].y +
+                 (double)x[i].z * (double)x[i].z + (double)x[i].w * (double)x[i].w;
+        }
+      }
+    } else if (s < S) {
       // dp is a multiple of 64: 8 values per lane per round, all loads of a
       // round issued before any is used
       for (int k0 = 0; k0 < p.dp; k0 += 64) {

@@ -67,7 +67,7 @@ __device__ __forceinline__ void sum_low(float (&x)[N]) {
 // Sum over lane bits [LO, 6) of a wave; bits below LO address different values.
 // Bits 2 and 3 together are row_ror:8 then row_ror:4 (a clean 4-lane sum only
 // when both are summed, which holds since the range always ends at bit 6).
-template <int LO, int N>
+template <int LO, int N, bool PERM = true>
 __device__ __forceinline__ void sum_high(float (&x)[N]) {
   if constexpr (LO <= 3) {
 #pragma unroll
@@ -85,13 +85,86 @@ __device__ __forceinline__ void sum_high(float (&x)[N]) {
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] += dpp<kDppXor1>(x[i]);
   }
-  if constexpr (LO <= 4) {
+  if constexpr (PERM && LO <= 4) {
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = add_xor16(x[i]);
   }
-  if constexpr (LO <= 5) {
+  if constexpr (PERM && LO <= 5) {
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = add_xor32(x[i]);
+  }
+}
+
+// x[e] / (sum over the permlane bits of den[e]) for e < N, where the bits are
+// bit 4 (M = 1), bit 5 (M = 2) or both (M = 3) and every other lane bit has
+// been summed already or addresses different values.  Instead of a full
+// reduction per element, 4 (M = 3) or 2 elements share one register: each
+// 16-lane group (half) ends up with the total of a different element, one
+// reciprocal serves them all, and the quotients are gathered back.  The
+// numerators come packed the same way (pack_high, once per item).
+template <int M, int N>
+struct HighPack {
+  static constexpr int NQ = M == 3 ? N / 4 : 0;               // groups of four elements
+  static constexpr int NP = M == 3 ? (N % 4) / 2 : N / 2;     // pairs
+  static constexpr int N1 = N % 2;                            // a last single element
+  static constexpr int P = NQ + NP + N1;
+};
+
+// sel ? b : a as a bit blend.  A plain select between two elements of one
+// register array can be turned into a load at a lane-dependent index, which
+// would move the whole array to scratch memory.
+__device__ __forceinline__ float pick(bool sel, float a, float b) {
+  const int m = -(int)sel;
+  return __int_as_float((__float_as_int(a) & ~m) | (__float_as_int(b) & m));
+}
+
+template <int M, int N>
+__device__ __forceinline__ void pack_high(const float (&x)[N], float (&xp)[HighPack<M, N>::P], int lane) {
+  using H = HighPack<M, N>;
+  const int g = (lane >> 4) & 3;
+#pragma unroll
+  for (int q = 0; q < H::NQ; ++q)
+    xp[q] = pick(g & 2, pick(g & 1, x[4 * q], x[4 * q + 1]), pick(g & 1, x[4 * q + 2], x[4 * q + 3]));
+#pragma unroll
+  for (int i = 0; i < H::NP; ++i) {
+    const int a = 4 * H::NQ + 2 * i;
+    const int sel = M == 2 ? (lane >> 5) & 1 : g & 1;
+    xp[H::NQ + i] = pick(sel, x[a], x[a + 1]);
+  }
+  if constexpr (H::N1 > 0) xp[H::NQ + H::NP] = x[N - 1];
+}
+
+template <int M, int N>
+__device__ __forceinline__ void high_div(const float (&np)[HighPack<M, N>::P], const float (&den)[N], float (&out)[N]) {
+  using H = HighPack<M, N>;
+#pragma unroll
+  for (int q = 0; q < H::NQ; ++q) {
+    const int a = 4 * q;
+    const float z = sum_scatter32(sum_scatter16(den[a], den[a + 1]), sum_scatter16(den[a + 2], den[a + 3]));
+    const float v = fast_div(np[q], z);
+    float lo, hi;
+    gather32(v, lo, hi);
+    gather16(lo, out[a], out[a + 1]);
+    gather16(hi, out[a + 2], out[a + 3]);
+  }
+#pragma unroll
+  for (int i = 0; i < H::NP; ++i) {
+    const int a = 4 * H::NQ + 2 * i;
+    if constexpr (M == 2) {
+      const float v = fast_div(np[H::NQ + i], sum_scatter32(den[a], den[a + 1]));
+      gather32(v, out[a], out[a + 1]);
+    } else {
+      float z = sum_scatter16(den[a], den[a + 1]);
+      if constexpr (M == 3) z = add_xor32(z);
+      const float v = fast_div(np[H::NQ + i], z);
+      gather16(v, out[a], out[a + 1]);
+    }
+  }
+  if constexpr (H::N1 > 0) {
+    float z = den[N - 1];
+    if constexpr (M & 1) z = add_xor16(z);
+    if constexpr (M & 2) z = add_xor32(z);
+    out[N - 1] = fast_div(np[H::NQ + H::NP], z);
   }
 }
 
@@ -183,6 +256,16 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       else
         u[e] = rv[e] > 0.f ? (float)vr : 0.f;  // x = 1/v_r
     }
+    // Reductions that cross the permlane bits (lane bits 4 and 5) divide in
+    // packed form: rows when the column lanes reach bit 4 (lg_cg >= 5), columns
+    // of one-wave items when the row lanes do (lg_cg <= 5).
+    constexpr bool ROWP = LG_CG >= 5;
+    constexpr bool COLP = !MW && LG_CG <= 5;
+    constexpr int MR = LG_CG == 5 ? 1 : 3;
+    constexpr int MC = LG_CG <= 4 ? 3 : 2;
+    float cpk[HighPack<MR, TR>::P], rpk[HighPack<MC, TC>::P];
+    if constexpr (ROWP) pack_high<MR, TR>(cw, cpk, lane);
+    if constexpr (COLP) pack_high<MC, TC>(rv, rpk, lane);
     float wv[TR];
     if (p.load_w) {
 #pragma unroll
@@ -204,9 +287,14 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
           for (int e = 0; e < TC; ++e) a = fmaf(K[t][e], u[e], a);
           s[t] = a;
         }
-        sum_low<LG_CG>(s);
+        if constexpr (ROWP) {
+          sum_low<4>(s);
+          high_div<MR, TR>(cpk, s, wv);
+        } else {
+          sum_low<LG_CG>(s);
 #pragma unroll
-        for (int t = 0; t < TR; ++t) wv[t] = fast_div(cw[t], s[t]);
+          for (int t = 0; t < TR; ++t) wv[t] = fast_div(cw[t], s[t]);
+        }
         if (p.store_w) {
           if (cg == 0 && active) {
 #pragma unroll
@@ -226,43 +314,51 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         for (int t = 0; t < TR; ++t) a = fmaf(K[t][e], wv[t], a);
         acc[e] = a;
       }
-      sum_high<LG_CG>(acc);
-      if constexpr (MAXW == 4) {
-        // cross-wave sum for at most 4 waves: every wave posts its column
-        // partials, then each lane adds the partials of its own columns in wave
-        // order; the buffer alternates by iteration parity, one barrier each
-        float* part = lds + (it & 1) * nwaves * cw_stride;
-        if (lane < CG) {
+      float un[TC];
+      if constexpr (COLP) {
+        sum_high<LG_CG, TC, false>(acc);
+        high_div<MC, TC>(rpk, acc, un);
+      } else {
+        sum_high<LG_CG>(acc);
+        if constexpr (MAXW == 4) {
+          // cross-wave sum for at most 4 waves: every wave posts its column
+          // partials, then each lane adds the partials of its own columns in wave
+          // order; the buffer alternates by iteration parity, one barrier each
+          float* part = lds + (it & 1) * nwaves * cw_stride;
+          if (lane < CG) {
 #pragma unroll
-          for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
-        }
-        __syncthreads();
+            for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
+          }
+          __syncthreads();
 #pragma unroll
-        for (int e = 0; e < TC; ++e) {
-          float a = 0.f;
-          for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + cg + CG * e];
-          acc[e] = a;
-        }
-      } else if constexpr (MW) {
-        // cross-wave sum in two phases for up to 16 waves: every wave posts its
-        // column partials, one thread per column adds them in wave order, every
-        // lane reads back its columns.  Both arrays alternate by iteration
-        // parity, so two barriers per iteration suffice.
-        float* part = lds + (it & 1) * nwaves * cw_stride;
-        float* tot = lds + 2 * nwaves * cw_stride + (it & 1) * cw_stride;
-        if (lane < CG) {
+          for (int e = 0; e < TC; ++e) {
+            float a = 0.f;
+            for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + cg + CG * e];
+            acc[e] = a;
+          }
+        } else if constexpr (MW) {
+          // cross-wave sum in two phases for up to 16 waves: every wave posts its
+          // column partials, one thread per column adds them in wave order, every
+          // lane reads back its columns.  Both arrays alternate by iteration
+          // parity, so two barriers per iteration suffice.
+          float* part = lds + (it & 1) * nwaves * cw_stride;
+          float* tot = lds + 2 * nwaves * cw_stride + (it & 1) * cw_stride;
+          if (lane < CG) {
 #pragma unroll
-          for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
-        }
-        __syncthreads();
-        for (int c = threadIdx.x; c < cw_stride; c += blockDim.x) {
-          float a = 0.f;
-          for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + c];
-          tot[c] = a;
-        }
-        __syncthreads();
+            for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
+          }
+          __syncthreads();
+          for (int c = threadIdx.x; c < cw_stride; c += blockDim.x) {
+            float a = 0.f;
+            for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + c];
+            tot[c] = a;
+          }
+          __syncthreads();
 #pragma unroll
-        for (int e = 0; e < TC; ++e) acc[e] = tot[cg + CG * e];
+          for (int e = 0; e < TC; ++e) acc[e] = tot[cg + CG * e];
+        }
+#pragma unroll
+        for (int e = 0; e < TC; ++e) un[e] = fast_div(rv[e], acc[e]);
       }
       if (p.tol > 0.f) {
         // "while x changes": x = 1/u, so |x_new - x| / x_new = |u - u_new| / u.
@@ -271,19 +367,22 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         float dm = 0.f;
 #pragma unroll
         for (int e = 0; e < TC; ++e) {
-          const float un = fast_div(rv[e], acc[e]);
-          if (rv[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un) * __builtin_amdgcn_rcpf(u[e]));
-          u[e] = un;
+          if (rv[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un[e]) * __builtin_amdgcn_rcpf(u[e]));
+          u[e] = un[e];
         }
         dm = max_low<LG_CG>(dm);
-        if (!(dm > p.tol)) {
+        // uniform over the wave (one item per wave, or the same value in every
+        // wave of a multi-wave item): a scalar branch, so the loop stays free
+        // of divergent-exit bookkeeping
+        const float dmu = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(dm)));
+        if (!(dmu > p.tol)) {
           ran = it + 1;
           break;
         }
         continue;
       }
 #pragma unroll
-      for (int e = 0; e < TC; ++e) u[e] = fast_div(rv[e], acc[e]);
+      for (int e = 0; e < TC; ++e) u[e] = un[e];
     }
 
     if (p.store_u && rs == 0 && active) {
