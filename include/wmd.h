@@ -88,7 +88,8 @@ typedef struct {
                                A document whose weights sum to 0 scores NaN.            */
   int32_t compact_vocab;    /* nonzero: evaluate the cost matrix only for the words
                                that occur in the corpus (results are identical)        */
-  void* workspace;          /* device, >= wmd_corpus_workspace_bytes(); holds the
+  void* workspace;          /* device, >= wmd_corpus_workspace_bytes(), 256-byte
+                               aligned (hipMalloc and torch allocations are); holds the
                                normalised weights, compacted embeddings (f32 + bf16),
                                squared norms and document-length buckets.  Borrowed.   */
   size_t workspace_bytes;
@@ -156,8 +157,9 @@ typedef struct {
 #define WMD_QUERY_GRAPH 1
 
 /* Bytes of query workspace for B queries with these offsets and schedule
- * (0 on invalid input).  Dominated by K^T and (K.*M)^T: 8 * U * sum_b S_b bytes,
- * S_b = entries of query b rounded up to a multiple of 4. */
+ * (0 on invalid input).  Dominated by K^T: 4 * U * sum_b S_b bytes, S_b =
+ * entries of query b rounded up to a multiple of 4 (the final pass recovers
+ * M from K, so no cost matrix is stored). */
 size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* q_ptr_host,
                                  int32_t schedule);
 
@@ -168,8 +170,9 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
  * Host-side argument errors are reported synchronously.  Errors found on the
  * device (a query id outside [0, V), a negative or non-finite weight, no
  * positive weight) make that query's row NaN and are read back with
- * wmd_query_errors().  Calls that share a workspace must be ordered on one
- * stream; calls with separate workspaces may run concurrently. */
+ * wmd_query_errors().  The workspace must be 256-byte aligned.  Calls that
+ * share a workspace must be ordered on one stream; calls with separate
+ * workspaces may run concurrently. */
 wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,
                      size_t workspace_bytes, void* stream);
 

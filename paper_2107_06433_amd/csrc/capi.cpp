@@ -157,6 +157,7 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
   if (need == 0) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus sizes overflow");
   if (D.workspace_bytes < need)
     return fail(WMD_ERR_WORKSPACE_TOO_SMALL, "corpus workspace needs " + std::to_string(need) + " bytes");
+  if ((uintptr_t)D.workspace % 256 != 0) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus workspace must be 256-byte aligned");
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   // doc_ptr is needed on the host for validation and the length buckets
@@ -334,6 +335,7 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
   const QueryLayout L = layout_for(c, plan, schedule);
   if (workspace_bytes < L.total)
     return fail(WMD_ERR_WORKSPACE_TOO_SMALL, "query workspace needs " + std::to_string(L.total) + " bytes");
+  if ((uintptr_t)workspace % 256 != 0) return fail(WMD_ERR_INVALID_ARGUMENT, "query workspace must be 256-byte aligned");
   int dev = 0;
   WMD_HIP(hipGetDevice(&dev));
   if (dev != c->device) return fail(WMD_ERR_INVALID_ARGUMENT, "current device differs from the corpus device");

@@ -168,6 +168,81 @@ __device__ __forceinline__ void high_div(const float (&np)[HighPack<M, N>::P], c
   }
 }
 
+// The same idea inside a lane quad, with DPP: x[e] / (sum over lane bit 0
+// (L = 1) or bits 0 and 1 (L = 2) of den[e]), optionally also summed over
+// lane bits 2 and 3 (HI23).  Lane q of a quad ends up with the total of
+// element 4i + q (or 2i + (q & 1)), divides once, and quad broadcasts give
+// every lane all the quotients.
+template <int L, int N>
+struct LowPack {
+  static constexpr int NQ = L == 2 ? N / 4 : 0;
+  static constexpr int NP = L == 2 ? (N % 4) / 2 : N / 2;
+  static constexpr int N1 = N % 2;
+  static constexpr int P = NQ + NP + N1;
+};
+
+template <int L, int N>
+__device__ __forceinline__ void pack_low(const float (&x)[N], float (&xp)[LowPack<L, N>::P], int lane) {
+  using H = LowPack<L, N>;
+  const int q = lane & 3;
+#pragma unroll
+  for (int i = 0; i < H::NQ; ++i)
+    xp[i] = pick(q & 2, pick(q & 1, x[4 * i], x[4 * i + 1]), pick(q & 1, x[4 * i + 2], x[4 * i + 3]));
+#pragma unroll
+  for (int i = 0; i < H::NP; ++i) {
+    const int a = 4 * H::NQ + 2 * i;
+    xp[H::NQ + i] = pick(q & 1, x[a], x[a + 1]);
+  }
+  if constexpr (H::N1 > 0) xp[H::NQ + H::NP] = x[N - 1];
+}
+
+template <int L, bool HI23, int N>
+__device__ __forceinline__ void low_div(const float (&np)[LowPack<L, N>::P], const float (&den)[N], float (&out)[N],
+                                        int lane) {
+  using H = LowPack<L, N>;
+  const bool b0 = lane & 1, b1 = lane & 2;
+  // lane parity b0 keeps element (b0 ? b : a) and hands its partner the other
+  auto pair0 = [&](float a, float b) {
+    // opaque copies: a select between two elements of one register array can
+    // become a load at a lane-dependent index (see pick)
+    asm("" : "+v"(a), "+v"(b));
+    return (b0 ? b : a) + dpp<kDppXor1>(b0 ? a : b);
+  };
+  auto hi23 = [&](float z) {
+    if constexpr (HI23) {
+      z += dpp<kDppRor8>(z);
+      z += dpp<kDppRor4>(z);
+    }
+    return z;
+  };
+#pragma unroll
+  for (int i = 0; i < H::NQ; ++i) {
+    const int a = 4 * i;
+    const float pab = pair0(den[a], den[a + 1]), pcd = pair0(den[a + 2], den[a + 3]);
+    const float z = hi23((b1 ? pcd : pab) + dpp<kDppXor2>(b1 ? pab : pcd));
+    const float v = fast_div(np[i], z);
+    out[a] = dpp<0x00>(v);      // quad_perm [0,0,0,0]
+    out[a + 1] = dpp<0x55>(v);  // quad_perm [1,1,1,1]
+    out[a + 2] = dpp<0xAA>(v);  // quad_perm [2,2,2,2]
+    out[a + 3] = dpp<0xFF>(v);  // quad_perm [3,3,3,3]
+  }
+#pragma unroll
+  for (int i = 0; i < H::NP; ++i) {
+    const int a = 4 * H::NQ + 2 * i;
+    float z = pair0(den[a], den[a + 1]);
+    if constexpr (L == 2) z += dpp<kDppXor2>(z);
+    const float v = fast_div(np[H::NQ + i], hi23(z));
+    out[a] = dpp<0xA0>(v);      // quad_perm [0,0,2,2]
+    out[a + 1] = dpp<0xF5>(v);  // quad_perm [1,1,3,3]
+  }
+  if constexpr (H::N1 > 0) {
+    float z = den[N - 1];
+    z += dpp<kDppXor1>(z);
+    if constexpr (L == 2) z += dpp<kDppXor2>(z);
+    out[N - 1] = fast_div(np[H::NQ + H::NP], hi23(z));
+  }
+}
+
 // Maximum over lane bits [0, NB), lower bits first (as sum_low).
 template <int NB>
 __device__ __forceinline__ float max_low(float x) {
@@ -233,12 +308,29 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       cw[t] = c > 0.f ? c : 0.f;
       rpad[t] = (wid[t] < 0 && cg == 0) ? 1.f : 0.f;
     }
+    // Columns of lane cg: the 4-column chunks cg, cg + CG, ... (4 TC4 columns,
+    // one 16-byte load per row each: S and every K^T row start are multiples
+    // of 4 floats) and then the single columns 4 CG TC4 + cg, ... + CG, ...
+    constexpr int TC4 = TC / 4;
+    auto col_of = [&](int e) {
+      return e < 4 * TC4 ? 4 * (cg + CG * (e >> 2)) + (e & 3) : 4 * CG * TC4 + cg + CG * (e - 4 * TC4);
+    };
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
       const float* row = p.kt + (size_t)(wid[t] < 0 ? 0 : wid[t]) * S;
 #pragma unroll
-      for (int e = 0; e < TC; ++e) {
-        const int col = cg + CG * e;
+      for (int c = 0; c < TC4; ++c) {
+        const int c0 = col_of(4 * c);
+        const float4 v = *(const float4*)(row + (c0 < S ? c0 : S - 4));  // clamped inside the row
+        const bool ok = wid[t] >= 0 && c0 < S;
+        K[t][4 * c] = ok ? v.x : 0.f;
+        K[t][4 * c + 1] = ok ? v.y : 0.f;
+        K[t][4 * c + 2] = ok ? v.z : 0.f;
+        K[t][4 * c + 3] = ok ? v.w : 0.f;
+      }
+#pragma unroll
+      for (int e = 4 * TC4; e < TC; ++e) {
+        const int col = col_of(e);
         const float v = row[col < S ? col : S - 1];  // clamped: never reads past the row
         K[t][e] = (wid[t] >= 0 && col < S) ? v : 0.f;
       }
@@ -248,7 +340,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     float rv[TC], u[TC], cpad[TC];
 #pragma unroll
     for (int e = 0; e < TC; ++e) {
-      const int col = cg + CG * e;
+      const int col = col_of(e);
       rv[e] = col < S ? p.r[col] : 0.f;
       cpad[e] = (rv[e] > 0.f || rs != 0) ? 0.f : 1.f;
       if (p.load_u)
@@ -266,6 +358,11 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     float cpk[HighPack<MR, TR>::P], rpk[HighPack<MC, TC>::P];
     if constexpr (ROWP) pack_high<MR, TR>(cw, cpk, lane);
     if constexpr (COLP) pack_high<MC, TC>(rv, rpk, lane);
+    // rows over 2 or 16 column lanes (lg_cg 1, 2 or 4) divide packed within quads
+    constexpr bool ROWQ = LG_CG == 1 || LG_CG == 2 || LG_CG == 4;
+    constexpr int LQ = LG_CG == 1 ? 1 : 2;
+    float cqk[LowPack<LQ, TR>::P];
+    if constexpr (ROWQ) pack_low<LQ, TR>(cw, cqk, lane);
     float wv[TR];
     if (p.load_w) {
 #pragma unroll
@@ -290,6 +387,8 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         if constexpr (ROWP) {
           sum_low<4>(s);
           high_div<MR, TR>(cpk, s, wv);
+        } else if constexpr (ROWQ) {
+          low_div<LQ, LG_CG == 4>(cqk, s, wv, lane);
         } else {
           sum_low<LG_CG>(s);
 #pragma unroll
@@ -388,7 +487,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     if (p.store_u && rs == 0 && active) {
 #pragma unroll
       for (int e = 0; e < TC; ++e) {
-        const int col = cg + CG * e;
+        const int col = col_of(e);
         if (col < S) p.u[(size_t)k * S + col] = u[e];
       }
     }

@@ -64,6 +64,9 @@ def test_host_argument_errors():
     desc.emb, desc.workspace_bytes = 1, 16
     assert lib.wmd_create_corpus(ctypes.byref(desc), None, ctypes.byref(out)) == 2
     assert b"workspace" in lib.wmd_last_error()
+    desc.workspace_bytes = 1 << 30  # large enough, but the pointer is not 256-byte aligned
+    assert lib.wmd_create_corpus(ctypes.byref(desc), None, ctypes.byref(out)) == 1
+    assert b"aligned" in lib.wmd_last_error()
     assert out.value is None
     q = wmd.QueryDesc(B=1, q_ptr_host=None, q_ptr=1, q_ids=1, q_weights=1, lam=10.0,
                       max_iter=15, cdist=0, schedule=0)
