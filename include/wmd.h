@@ -230,9 +230,10 @@ typedef struct {
 wmd_status wmd_sink_candidates(const wmd_corpus* c, int32_t S, int32_t cap, wmd_sink_shape* out, int32_t capacity,
                                int32_t* count);
 
-/* Pins the shape this corpus uses for (S, cap), e.g. from a measured tuning
- * table; NULL removes the pin.  A shape that cannot run (S, cap) is rejected
- * with WMD_ERR_INVALID_ARGUMENT. */
+/* Pins the shape this corpus uses for (S, cap) when that bucket launches on
+ * its own (see wmd_set_merge), e.g. from a measured tuning table; NULL removes
+ * the pin.  A shape that cannot run (S, cap) is rejected with
+ * WMD_ERR_INVALID_ARGUMENT. */
 wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_sink_shape* shape);
 
 /* How a query's length buckets are grouped into Sinkhorn launches.  Work
@@ -243,7 +244,8 @@ wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_s
  *                   (up to 16 rows per lane) joins one launch per query, the
  *                   longest documents first (default)
  *   WMD_MERGE_NONE: one launch per bucket
- * Buckets with a pinned shape always launch on their own. */
+ * Pinned shapes (wmd_set_sink_shape) apply to the buckets that launch on
+ * their own. */
 #define WMD_MERGE_ALL 0
 #define WMD_MERGE_NONE 1
 wmd_status wmd_set_merge(wmd_corpus* c, int32_t mode);

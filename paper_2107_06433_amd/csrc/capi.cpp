@@ -407,7 +407,6 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
     for (int bk = 0; bk < kNumBuckets; ++bk) {
       const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
       if (nd == 0) continue;
-      if (c->pinned.count({S, kBucketCap[bk]})) continue;
       caps[nm] = kBucketCap[bk]; nds[nm] = (int)nd; bks[nm] = bk; ++nm;
     }
     bool in_merge[kNumBuckets] = {};

@@ -4,8 +4,10 @@
 
 For every (padded query width S, document-length bucket) pair that a
 workload's queries meet, each candidate shape the library offers is timed
-(HIP events around the launches) on the workload's own corpus, and the
-fastest is kept.  Entries are keyed by (S, bucket capacity, log2 of the
+(HIP events around the launches, one launch per bucket) on the workload's own
+corpus, and the fastest is kept.  The pins apply to buckets that launch on
+their own; buckets that share a query's merged launch keep the merged
+kernel's shape.  Entries are keyed by (S, bucket capacity, log2 of the
 bucket's document count), because the best shape depends on how many
 documents one launch holds.  The table is written to
 paper_2107_06433_amd/tuning/gfx950_sink_shapes.json, which Corpus applies
@@ -56,6 +58,7 @@ def tune_workload(name: str, cdist: str = "fp32", reps: int = 2, max_candidates:
     w = synth.make_workload(name)
     c = w.corpus
     corpus = wmd.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, c.weights, tuning=None)
+    corpus.set_merge("none")  # every bucket on its own, so each pinned shape is timed
     info = corpus.info()
     bucket_docs = dict(zip(info["bucket_cap"], info["bucket_docs"]))
     Q = w.queries if w.queries.B <= max_queries else representative_queries(w.queries, max_queries)
