@@ -217,19 +217,27 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
   const int vpr = dp * ESZ / 16;
   const int qtotal = NT * 16 * vpr;
+  // i / vpr by a float reciprocal and one correction step (exact for i < 2^22)
+  const float rvpr = 1.0f / (float)vpr;
+  auto row_of = [&](int i) {
+    int r = (int)((float)i * rvpr);
+    r -= r * vpr > i;
+    r += (r + 1) * vpr <= i;
+    return r;
+  };
   for (int i0 = 0; i0 < qtotal; i0 += 8 * 256) {
     uint4 qv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = i0 + j * 256 + tid;
-      const int row = i / vpr;
+      const int row = row_of(i);
       qv[j] = (i < qtotal && row < p.C) ? *(const uint4*)(Qg + (size_t)row * row_bytes + 16 * (i - row * vpr))
                                         : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = i0 + j * 256 + tid;
-      const int row = i / vpr;
+      const int row = row_of(i);
       if (i < qtotal) *(uint4*)(smem + row * ldq + 16 * (i - row * vpr)) = qv[j];
     }
   }

@@ -98,35 +98,36 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
   __shared__ int s_id[kMaxQueryLen];
   __shared__ float s_w[kMaxQueryLen];
   __shared__ double s_m[kMaxQueryLen];
-  __shared__ int s_pos[kMaxQueryLen];
   __shared__ int s_slot[kMaxQueryLen];
-  __shared__ long long s_red[256];
-  __shared__ double s_dred[256];
-  __shared__ int s_err;
+  __shared__ int s_wflag[4];
+  __shared__ long long s_col0;
+  __shared__ int s_vr, s_err;
+  __shared__ double s_tot;
   const int b = blockIdx.x;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t beg = p.q_ptr[b];
   const int n = (int)(p.q_ptr[b + 1] - beg);
-  // column base of this query: sum of the padded widths of the queries before it
-  long long part = 0;
-  for (int bb = t; bb < b; bb += 256) part += (p.q_ptr[bb + 1] - p.q_ptr[bb] + 3) & ~3LL;
-  s_red[t] = part;
-  if (t == 0) s_err = 0;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off) s_red[t] += s_red[t + off];
-    __syncthreads();
-  }
-  const int64_t col0 = s_red[0];
   const int S = (n + 3) & ~3;
   const int nn = n < kMaxQueryLen ? n : kMaxQueryLen;
+  // entries into LDS, with their error flags ORed per wave
+  int lf = 0;
   for (int i = t; i < nn; i += 256) {
     const int id = p.q_ids[beg + i];
     const float x = p.q_w[beg + i];
     s_id[i] = id;
     s_w[i] = x;
-    if (id < 0 || id >= p.V) atomicOr(&s_err, 1);
-    if (!(x >= 0.f) || isinf(x)) atomicOr(&s_err, 2);
+    if (id < 0 || id >= p.V) lf |= 1;
+    if (!(x >= 0.f) || isinf(x)) lf |= 2;
+  }
+  const bool f1 = __ballot(lf & 1) != 0, f2 = __ballot(lf & 2) != 0;
+  if (lane == 0) s_wflag[wave] = (f1 ? 1 : 0) | (f2 ? 2 : 0);
+  // column base of this query: the padded widths of the queries before it,
+  // summed by the last wave (lane partials, then a fixed butterfly)
+  if (wave == 3) {
+    long long part = 0;
+    for (int bb = lane; bb < b; bb += 64) part += (p.q_ptr[bb + 1] - p.q_ptr[bb] + 3) & ~3LL;
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane == 0) s_col0 = part;
   }
   __syncthreads();
   // merge repeats into their first occurrence, summing in entry order
@@ -142,36 +143,43 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
     s_m[i] = first ? m : 0.0;
   }
   __syncthreads();
-  // slot of every selected entry, in entry order; total weight in a fixed order
-  if (t == 0) {
+  // slots in entry order and the total weight, by the first wave: per chunk
+  // of 64 entries a ballot prefix and a fixed butterfly sum, chunks in order
+  if (wave == 0) {
     int c = 0;
     double tot = 0.0;
-    for (int i = 0; i < nn; ++i) {
-      if (s_m[i] > 0.0) { s_pos[i] = c++; tot += s_m[i]; }
-      else s_pos[i] = -1;
+    for (int i0 = 0; i0 < nn; i0 += 64) {
+      const int i = i0 + lane;
+      const double m = i < nn ? s_m[i] : 0.0;
+      const bool sel = m > 0.0;
+      const unsigned long long mask = __ballot(sel);
+      if (sel) s_slot[c + __popcll(mask & ((1ull << lane) - 1))] = i;
+      c += __popcll(mask);
+      double part = sel ? m : 0.0;
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+      tot += part;
     }
-    s_red[0] = c;
-    s_dred[0] = tot;
-    if (n > kMaxQueryLen) s_err |= 4;
-    if (s_err == 0 && c == 0) s_err = 8;
+    for (int k = c + lane; k < S && k < kMaxQueryLen; k += 64) s_slot[k] = -1;
+    if (lane == 0) {
+      int e = s_wflag[0] | s_wflag[1] | s_wflag[2] | s_wflag[3];
+      if (n > kMaxQueryLen) e |= 4;
+      if (e == 0 && c == 0) e = 8;
+      s_err = e;
+      s_vr = e ? 0 : c;
+      s_tot = tot;
+    }
   }
   __syncthreads();
   const int err = s_err;
-  const int vr = err ? 0 : (int)s_red[0];
-  const double tot = s_dred[0];
+  const int vr = s_vr;
+  const double tot = s_tot;
+  const int64_t col0 = s_col0;
   if (t == 0) {
     p.err[b] = err & 1 ? 1 : err & 2 ? 2 : err & 4 ? 4 : err & 8 ? 3 : 0;
     p.vr[b] = vr;
   }
-  // slot -> vocabulary id, kept in LDS for the row copies below
-  for (int s = t; s < S; s += 256) s_slot[s] = -1;
-  __syncthreads();
-  if (vr > 0)
-    for (int i = t; i < nn; i += 256)
-      if (s_pos[i] >= 0) s_slot[s_pos[i]] = i;
-  __syncthreads();
   for (int s = t; s < S; s += 256) {
-    const int i = s_slot[s];
+    const int i = s < vr && s < kMaxQueryLen ? s_slot[s] : -1;
     p.qid[col0 + s] = i >= 0 ? s_id[i] : -1;
     p.r[col0 + s] = i >= 0 ? (float)(s_m[i] / tot) : 0.f;
     p.cinfo[col0 + s] = make_int2((int)col0, S);
@@ -182,7 +190,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
   const int g = t >> 3, lane8 = t & 7;
   for (int s0 = 0; s0 < S; s0 += 32) {
     const int s = s0 + g;
-    const int i = s < S ? s_slot[s] : -1;
+    const int i = s < vr && s < kMaxQueryLen ? s_slot[s] : -1;
     const int q = i >= 0 ? s_id[i] : -1;
     const float* src = p.emb + (size_t)(q < 0 ? 0 : q) * p.d;
     double nrm = 0.0;

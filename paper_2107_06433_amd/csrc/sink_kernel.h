@@ -255,12 +255,15 @@ __device__ __forceinline__ float max_low(float x) {
   return x;
 }
 
-// The cost M of a kernel entry K = exp(-lambda M), recovered as -ln(K) / lambda.
-// K = 1 (the same word) gives exactly 0; an entry at or below the smallest
-// normal float contributes K * M ~ 0 and is dropped.
-__device__ __forceinline__ float cost_from_gibbs(float k, float inv_lam) {
-  return k > 1.17549435e-38f ? -__logf(k) * inv_lam : 0.f;
+// The cost M of a kernel entry K = exp(-lambda M) is -ln(K) / lambda =
+// log2(K) * (-ln 2 / lambda).  The final pass sums K u log2(K) and applies the
+// constant once per document.  K = 1 (the same word) gives exactly 0; K is
+// clamped to the smallest normal float first, so an underflowed entry (or a
+// padding zero) adds K u * (-126) ~ 0 instead of 0 * inf.
+__device__ __forceinline__ float log2_gibbs(float k) {
+  return __builtin_amdgcn_logf(fmaxf(k, 1.17549435e-38f));
 }
+constexpr float kNegLn2 = -0.693147180559945309f;
 
 __device__ __forceinline__ int64_t rec_begin(const int4& r) {
   return (int64_t)(uint32_t)r.x | ((int64_t)r.y << 32);
@@ -503,7 +506,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         for (int e = 0; e < TC; ++e) {
           const float ku = K[t][e] * u[e];
           a += ku;
-          b = fmaf(ku, cost_from_gibbs(K[t][e], p.inv_lam), b);
+          b = fmaf(ku, log2_gibbs(K[t][e]), b);
         }
         sa[t] = a;
         sb[t] = b;
@@ -525,6 +528,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         tot = a;
         __syncthreads();
       }
+      tot *= kNegLn2 * p.inv_lam;
       if (lane == 0 && (MW ? wave == 0 : true) && active) {
         p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
         if (p.iters_out) p.iters_out[k] = ran;

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) sink_stream_kernel(SinkParams p) {
         for (int c = lane; c < S; c += 64) {
           const float ku = row[c] * su[c];
           a += ku;
-          b = fmaf(ku, cost_from_gibbs(row[c], p.inv_lam), b);
+          b = fmaf(ku, log2_gibbs(row[c]), b);
         }
         a = sum_wave(a);
         b = sum_wave(b);
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) sink_stream_kernel(SinkParams p) {
       if (lane == 0) sred[wave] = part;
       __syncthreads();
       if (threadIdx.x == 0) {
-        const float tot = ((sred[0] + sred[1]) + sred[2]) + sred[3];
+        const float tot = (((sred[0] + sred[1]) + sred[2]) + sred[3]) * (kNegLn2 * p.inv_lam);
         p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
         if (p.iters_out) p.iters_out[k] = p.iters;  // no tolerance stop on this path
       }
