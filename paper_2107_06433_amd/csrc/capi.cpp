@@ -619,7 +619,7 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
   for (const auto& p : c->pinned) {
     key.push_back(((uint64_t)p.first.first << 32) | (uint32_t)p.first.second);
     key.push_back(((uint64_t)p.second.tc << 48) | ((uint64_t)p.second.tr << 32) | ((uint64_t)p.second.lg_cg << 16) |
-                  ((uint64_t)p.second.nwaves << 4) | (uint64_t)p.second.maxw);
+                  ((uint64_t)p.second.nwaves << 8) | (uint64_t)p.second.maxw);
   }
   int dev = 0;
   WMD_HIP(hipGetDevice(&dev));

@@ -539,7 +539,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
 
 // Multi-wave items: one item per block of up to MAXW waves.
 template <int TC, int TR, int LG_CG, int MAXW>
-__global__ void __launch_bounds__(MAXW == 16 ? 1024 : 256) sink_kernel(SinkParams p) {
+__global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
   sink_body<TC, TR, LG_CG, MAXW>(p, blockIdx.x, gridDim.x);
 }
 
@@ -590,7 +590,7 @@ struct SinkEntry {
 
 // Register budget per lane of the K^T block: up to 128 cells with at most 4
 // waves per block (up to 512 VGPRs per lane), up to 64 cells in 16-wave
-// blocks (128 VGPRs per lane).
+// blocks (128 VGPRs per lane).  Shapes that still spill are never chosen.
 template <int TC, int TR, int MAXW>
 constexpr bool kSinkFits = TC * TR <= (MAXW == 16 ? 64 : 128);
 
