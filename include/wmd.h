@@ -218,7 +218,7 @@ wmd_status wmd_get_launches(wmd_corpus* c, wmd_launch_rec* recs, int32_t capacit
 /* A shape of the fused Sinkhorn kernel: each lane keeps tc query words x tr
  * document words of K^T in registers; 2^lg_cg lanes span the query words; a
  * document occupies one wave (maxw = 1, four documents per block) or nwaves
- * waves of a block compiled for at most maxw (4 or 16) waves.  stream = 1 is
+ * waves of a block compiled for at most maxw (4, 8 or 16) waves.  stream = 1 is
  * the fallback that re-reads K^T rows on every pass (other fields ignored). */
 typedef struct {
   int32_t tc, tr, lg_cg, maxw, nwaves, stream;

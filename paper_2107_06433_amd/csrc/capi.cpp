@@ -444,7 +444,8 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
       const SinkConfig& cfg = u.cfg;
       u.name = cfg.stream ? std::string("sink_stream_kernel")
                           : cfg.multiwave ? "sink_kernel<" + std::to_string(cfg.tc) + "," + std::to_string(cfg.tr) +
-                                                "," + std::to_string(cfg.lg_cg) + ">x" + std::to_string(cfg.nwaves)
+                                                "," + std::to_string(cfg.lg_cg) + "," + std::to_string(cfg.maxw) +
+                                                ">x" + std::to_string(cfg.nwaves)
                                           : "sink_merge_kernel<" + std::to_string(cfg.tc) + "," +
                                                 std::to_string(cfg.tr) + "," + std::to_string(cfg.lg_cg) + ">x1";
       units[(size_t)b].push_back(std::move(u));

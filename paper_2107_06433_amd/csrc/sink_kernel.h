@@ -422,27 +422,13 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         high_div<MC, TC>(rpk, acc, un);
       } else {
         sum_high<LG_CG>(acc);
-        if constexpr (MAXW == 4) {
-          // cross-wave sum for at most 4 waves: every wave posts its column
-          // partials, then each lane adds the partials of its own columns in wave
-          // order; the buffer alternates by iteration parity, one barrier each
-          float* part = lds + (it & 1) * nwaves * cw_stride;
-          if (lane < CG) {
-#pragma unroll
-            for (int e = 0; e < TC; ++e) part[wave * cw_stride + cg + CG * e] = acc[e];
-          }
-          __syncthreads();
-#pragma unroll
-          for (int e = 0; e < TC; ++e) {
-            float a = 0.f;
-            for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + cg + CG * e];
-            acc[e] = a;
-          }
-        } else if constexpr (MW) {
-          // cross-wave sum in two phases for up to 16 waves: every wave posts its
-          // column partials, one thread per column adds them in wave order, every
-          // lane reads back its columns.  Both arrays alternate by iteration
-          // parity, so two barriers per iteration suffice.
+        if constexpr (MW) {
+          // cross-wave sum in two phases: every wave posts its column partials,
+          // one thread per column adds them in wave order, every lane reads back
+          // its columns.  Both arrays alternate by iteration parity, so two
+          // barriers per iteration suffice.  (Measured faster than one barrier
+          // with every lane adding all waves' partials of its columns, even
+          // for 4 waves.)
           float* part = lds + (it & 1) * nwaves * cw_stride;
           float* tot = lds + 2 * nwaves * cw_stride + (it & 1) * cw_stride;
           if (lane < CG) {
@@ -584,18 +570,18 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
 
 struct SinkEntry {
   int tc, tr, lg_cg;
-  int maxw;       // 1: one wave per item (sink_merge_kernel, TRMAX = tr); 4 or 16: waves per block at most
+  int maxw;       // 1: one wave per item (sink_merge_kernel, TRMAX = tr); 4, 8 or 16: waves per block at most
   const void* fn;
 };
 
-// Register budget per lane of the K^T block: up to 128 cells with at most 4
-// waves per block (up to 512 VGPRs per lane), up to 64 cells in 16-wave
+// Register budget per lane of the K^T block: up to 128 cells in blocks of at
+// most 4 or 8 waves (512 or 256 VGPRs per lane), up to 64 cells in 16-wave
 // blocks (128 VGPRs per lane).  Shapes that still spill are never chosen.
 template <int TC, int TR, int MAXW>
 constexpr bool kSinkFits = TC * TR <= (MAXW == 16 ? 64 : 128);
 
 #define WMD_SINK_SW_TR(X, TC, LG) X(TC, 1, LG, 1) X(TC, 2, LG, 1) X(TC, 4, LG, 1) X(TC, 8, LG, 1) X(TC, 16, LG, 1)
-#define WMD_SINK_MW_TR(X, TC, LG) X(TC, 8, LG, 4) X(TC, 16, LG, 4) X(TC, 4, LG, 16) X(TC, 8, LG, 16)
+#define WMD_SINK_MW_TR(X, TC, LG) X(TC, 8, LG, 4) X(TC, 16, LG, 4) X(TC, 8, LG, 8) X(TC, 4, LG, 16) X(TC, 8, LG, 16)
 #define WMD_SINK_TC(X, TC, LG) WMD_SINK_SW_TR(X, TC, LG) WMD_SINK_MW_TR(X, TC, LG)
 
 template <int TC, int TR, int LG_CG, int MAXW, bool OK = kSinkFits<TC, TR, MAXW>>
