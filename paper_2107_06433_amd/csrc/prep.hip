@@ -1,6 +1,7 @@
 // Corpus preparation (run once by wmd_create_corpus) and query selection
 // (the first step of every wmd_query).
 #include "lanes.h"
+#include "query_rows.h"
 #include "wmd_internal.h"
 
 namespace wmd {
@@ -185,60 +186,23 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
     p.cinfo[col0 + s] = make_int2((int)col0, S);
   }
   // embedding rows of the slots and their squared norms: 8 lanes per slot,
-  // 32 slots per pass, every row load of a pass in flight together; the norm
-  // is a double sum in a fixed order (strided partials, then a 3-step tree)
+  // 32 slots per pass (query_row)
   const int g = t >> 3, lane8 = t & 7;
   for (int s0 = 0; s0 < S; s0 += 32) {
     const int s = s0 + g;
     const int i = s < vr && s < kMaxQueryLen ? s_slot[s] : -1;
     const int q = i >= 0 ? s_id[i] : -1;
-    const float* src = p.emb + (size_t)(q < 0 ? 0 : q) * p.d;
     double nrm = 0.0;
-    if (s < S && (p.d & 3) == 0 && ((uintptr_t)p.emb & 15) == 0 && p.dp <= 512) {
-      // rows of 16-byte pieces: piece lane8 + 8 i of the row for i < 16, every
-      // load of the row issued before the first store
-      float4 x[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int k = 4 * (lane8 + 8 * i);
-        x[i] = (q >= 0 && k < p.d) ? *(const float4*)(src + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int k = 4 * (lane8 + 8 * i);
-        if (k < p.dp) {
-          *(float4*)(p.q32 + (size_t)(col0 + s) * p.dp + k) = x[i];
-          if (p.want_bf16) {
-            const uint32_t lo = (uint32_t)f32_to_bf16(x[i].x) | ((uint32_t)f32_to_bf16(x[i].y) << 16);
-            const uint32_t hi = (uint32_t)f32_to_bf16(x[i].z) | ((uint32_t)f32_to_bf16(x[i].w) << 16);
-            *(uint2*)(p.q16 + (size_t)(col0 + s) * p.dp + k) = make_uint2(lo, hi);
-          }
-          nrm += (double)x[i].x * (double)x[i].x + (double)x[i].y * (double)x[i].y +
-                 (double)x[i].z * (double)x[i].z + (double)x[i].w * (double)x[i].w;
-        }
-      }
-    } else if (s < S) {
-      // dp is a multiple of 64: 8 values per lane per round, all loads of a
-      // round issued before any is used
-      for (int k0 = 0; k0 < p.dp; k0 += 64) {
-        float x[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = k0 + lane8 + 8 * i;
-          x[i] = (q >= 0 && k < p.d) ? src[k] : 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = k0 + lane8 + 8 * i;
-          p.q32[(size_t)(col0 + s) * p.dp + k] = x[i];
-          if (p.want_bf16) p.q16[(size_t)(col0 + s) * p.dp + k] = f32_to_bf16(x[i]);
-          nrm += (double)x[i] * (double)x[i];
-        }
-      }
+    if (s < S) {
+      float* d32 = p.q32 + (size_t)(col0 + s) * p.dp;
+      uint16_t* d16 = p.q16 + (size_t)(col0 + s) * p.dp;
+      const bool bf = p.want_bf16;
+      nrm = query_row(p.emb, p.d, p.dp, q, lane8, [&](int k, float4 v) {
+        *(float4*)(d32 + k) = v;
+        if (bf) *(uint2*)(d16 + k) = pack_bf16x4(v);
+      });
     }
-    nrm += __shfl_xor(nrm, 1, 8);
-    nrm += __shfl_xor(nrm, 2, 8);
-    nrm += __shfl_xor(nrm, 4, 8);
+    nrm = sum_row_lanes(nrm);
     if (s < S && lane8 == 0) p.qn[col0 + s] = (float)nrm;
   }
 }

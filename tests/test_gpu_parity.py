@@ -316,6 +316,26 @@ def test_merged_launches_match_separate_launches(W):
         assert_close(merged[b, docs], ref, TOL32, f"merged, query width {len(ids)}")
 
 
+@pytest.mark.parametrize("d", [37, 130])
+def test_embedding_widths_off_the_vector_path(W, d):
+    """Widths that are not a multiple of 4 take the scalar row copies in query
+    selection; 130 also pads to 192 columns in the cost matrix."""
+    rng = np.random.default_rng(45 + d)
+    c = handmade_corpus(rng, 3000, d, rng.integers(1, 90, size=120))
+    qs = [rng.choice(3000, size=v, replace=False) for v in (6, 25, 40)]
+    q = synth.Queries(q_ptr=np.concatenate([[0], np.cumsum([len(x) for x in qs])]),
+                      ids=np.concatenate(qs).astype(np.int32),
+                      weights=rng.integers(1, 4, size=sum(len(x) for x in qs)).astype(np.float32))
+    corpus = corpus_of(W, c)
+    got32 = run(W, corpus, q, 10.0, 15)
+    got16 = run(W, corpus, q, 10.0, 15, cdist="bf16")
+    for b in range(q.B):
+        ids, qw = q.query(b)
+        ref = oracle_support(c, ids, qw, 10.0, 15)
+        assert_close(got32[b], ref, TOL32, f"d={d} fp32 query {b}")
+        assert_close(got16[b], ref, TOL16, f"d={d} bf16 query {b}")
+
+
 @pytest.mark.parametrize("vr", [1, 3, 4, 5, 63, 64, 65, 500, 2048])
 def test_query_widths(W, vr):
     rng = np.random.default_rng(43 + vr)
