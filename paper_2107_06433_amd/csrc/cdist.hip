@@ -191,11 +191,13 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
 // is staged in LDS first; then all loads of a row (up to 24 steps) are issued
 // at once, before the epilogue's per-row data is fetched, so one memory
 // latency covers the whole row.
-template <int NT, bool BF16>
+template <int NT, bool BF16, int CH>
 __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   constexpr int ESZ = BF16 ? 2 : 4;
   constexpr int KS = BF16 ? 32 : 16;        // k values per 16-byte-per-lane load step
-  constexpr int CH = 24;                    // load steps per chunk: a whole row for dp <= 384 (f32) / 768 (bf16)
+  // CH = dp / KS load steps: the whole row, a compile-time count, and every
+  // load unconditional (rows past U read row 0 and are never stored), so the
+  // MFMA of step i waits only for load i
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int dp = p.dp;
@@ -206,7 +208,6 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   const bool row_ok = myrow < p.U;
   const unsigned char* Ag = (BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32) +
                             (size_t)(row_ok ? myrow : 0) * row_bytes + 16 * (lane >> 4);
-  const int nsteps = dp / KS;
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -242,28 +243,23 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     }
   }
   uint4 buf[CH];
-  auto load = [&](int s0) {
 #pragma unroll
-    for (int i = 0; i < CH; ++i)
-      buf[i] = (row_ok && s0 + i < nsteps) ? *(const uint4*)(Ag + (size_t)(s0 + i) * 64) : make_uint4(0, 0, 0, 0);
-  };
-  load(0);
+  for (int i = 0; i < CH; ++i) buf[i] = *(const uint4*)(Ag + (size_t)i * 64);
   // the epilogue's per-row data, fetched early for the same reason
   float en_r[4];
   int used_r[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t m = m0 + 4 * (lane >> 4) + i;
-    en_r[i] = m < p.U ? p.en[m] : 0.f;
-    used_r[i] = m < p.U ? p.used[m] : -1;
+    const int64_t mc = m < p.U ? m : p.U - 1;
+    en_r[i] = p.en[mc];
+    used_r[i] = p.used[mc];
   }
   __syncthreads();
-  for (int s0 = 0; s0 < nsteps; s0 += CH) {
-    if (s0 > 0) load(s0);  // rows longer than one chunk: next chunk after this one's MFMAs
+  {
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
-      if (s0 + i >= nsteps) break;
-      const int kb = (s0 + i) * 64 + 16 * (lane >> 4);  // byte offset of this lane's k run
+      const int kb = i * 64 + 16 * (lane >> 4);  // byte offset of this lane's k run
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const uint4 q = *(const uint4*)(smem + (t * 16 + (lane & 15)) * ldq + kb);
@@ -303,12 +299,45 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   }
 }
 
-template <int NT, bool BF16>
-hipError_t run_skinny(const CdistParams& p, hipStream_t s) {
+template <int NT, bool BF16, int CH>
+hipError_t run_skinny_ch(const CdistParams& p, hipStream_t s) {
   const size_t lds = (size_t)NT * 16 * (p.dp * (BF16 ? 2 : 4) + 16);
   const unsigned grid = (unsigned)((p.U + 63) / 64);
-  cdist_skinny_kernel<NT, BF16><<<grid, 256, lds, s>>>(p);
+  cdist_skinny_kernel<NT, BF16, CH><<<grid, 256, lds, s>>>(p);
   return hipGetLastError();
+}
+
+// the skinny kernel instantiated for this row length (dp / (16 / elem bytes)
+// load steps), or hipErrorInvalidValue when there is none
+template <int NT, bool BF16>
+hipError_t run_skinny(const CdistParams& p, hipStream_t s) {
+  const int steps = p.dp / (BF16 ? 32 : 16);
+  switch (steps) {
+    case 4: return run_skinny_ch<NT, BF16, 4>(p, s);
+    case 8: return run_skinny_ch<NT, BF16, 8>(p, s);
+    case 12: return run_skinny_ch<NT, BF16, 12>(p, s);
+    case 16: return run_skinny_ch<NT, BF16, 16>(p, s);
+    case 20: return run_skinny_ch<NT, BF16, 20>(p, s);
+    case 24: return run_skinny_ch<NT, BF16, 24>(p, s);
+    default: break;
+  }
+  if constexpr (BF16) {
+    switch (steps) {
+      case 2: return run_skinny_ch<NT, BF16, 2>(p, s);
+      case 6: return run_skinny_ch<NT, BF16, 6>(p, s);
+      case 10: return run_skinny_ch<NT, BF16, 10>(p, s);
+      case 14: return run_skinny_ch<NT, BF16, 14>(p, s);
+      case 18: return run_skinny_ch<NT, BF16, 18>(p, s);
+      case 22: return run_skinny_ch<NT, BF16, 22>(p, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+bool skinny_steps_ok(int dp, bool bf16) {
+  const int steps = dp / (bf16 ? 32 : 16);
+  return steps >= (bf16 ? 2 : 4) && steps <= 24 && steps % (bf16 ? 2 : 4) == 0;
 }
 
 }  // namespace
@@ -316,11 +345,12 @@ hipError_t run_skinny(const CdistParams& p, hipStream_t s) {
 hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name) {
   if (p.U <= 0 || p.C <= 0) return hipSuccess;
   const size_t skinny_lds = (size_t)32 * (p.dp * (bf16 ? 2 : 4) + 16);
-  if (p.C <= 16 && skinny_lds / 2 <= 65536) {
+  const bool skinny = skinny_steps_ok(p.dp, bf16);
+  if (skinny && p.C <= 16 && skinny_lds / 2 <= 65536) {
     *name = bf16 ? "cdist_skinny_kernel<1,1>" : "cdist_skinny_kernel<1,0>";
     return bf16 ? run_skinny<1, true>(p, s) : run_skinny<1, false>(p, s);
   }
-  if (p.C <= 32 && skinny_lds <= 65536) {
+  if (skinny && p.C <= 32 && skinny_lds <= 65536) {
     *name = bf16 ? "cdist_skinny_kernel<2,1>" : "cdist_skinny_kernel<2,0>";
     return bf16 ? run_skinny<2, true>(p, s) : run_skinny<2, false>(p, s);
   }
