@@ -187,10 +187,8 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
 // Few query columns (C <= 32): the GEMM is a stream over the U x dp vocabulary
 // rows.  Each wave owns 16 rows and reads them straight from memory into the
 // MFMA operand registers -- for every 16 (f32) or 32 (bf16) k values, the four
-// lane quads of a row read one contiguous 64-byte piece.  Q (at most 32 rows)
-// is staged in LDS first; then all loads of a row (up to 24 steps) are issued
-// at once, before the epilogue's per-row data is fetched, so one memory
-// latency covers the whole row.
+// lane quads of a row read one contiguous 64-byte piece.  All loads of a row
+// (CH steps) are issued at once, so one memory latency covers the whole row.
 template <int NT, bool BF16, int CH>
 __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   constexpr int ESZ = BF16 ? 2 : 4;
@@ -198,49 +196,34 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   // CH = dp / KS load steps: the whole row, a compile-time count, and every
   // load unconditional (rows past U read row 0 and are never stored), so the
   // MFMA of step i waits only for load i
+  constexpr int ROWB = CH * KS * ESZ;       // bytes per embedding row (64 per step)
+  constexpr int LDQ = ROWB + 16;            // LDS row pitch in bytes (one 16-byte pad)
+  constexpr int VPR = ROWB / 16;            // 16-byte pieces per row
+  constexpr int QTOT = NT * 16 * VPR;       // pieces of the Q tile
+  constexpr int QPT = (QTOT + 255) / 256;   // per thread
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int dp = p.dp;
-  const size_t row_bytes = (size_t)dp * ESZ;
-  const int ldq = dp * ESZ + 16;            // LDS row pitch in bytes (one 16-byte pad)
   const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   const int64_t myrow = m0 + (lane & 15);
   const bool row_ok = myrow < p.U;
   const unsigned char* Ag = (BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32) +
-                            (size_t)(row_ok ? myrow : 0) * row_bytes + 16 * (lane >> 4);
+                            (size_t)(row_ok ? myrow : 0) * ROWB + 16 * (lane >> 4);
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // Q: NT*16 rows (zero beyond C) go to LDS first, eight 16-byte pieces per
-  // thread in flight at a time (one L2 round trip for typical widths), before
-  // any vocabulary load: loads complete in order, so Q pieces issued behind the
-  // vocabulary row would wait for all of it.
+  // Q: NT*16 rows go to LDS through registers.  Its loads are issued first
+  // and its LDS stores come after the vocabulary row's loads: loads retire in
+  // order, so the stores wait for the Q pieces alone while the row is already
+  // in flight.  Rows past C repeat Q's first piece: each output column depends
+  // on its own Q row only, and the epilogue never stores those columns.
   const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
-  const int vpr = dp * ESZ / 16;
-  const int qtotal = NT * 16 * vpr;
-  // i / vpr by a float reciprocal and one correction step (exact for i < 2^22)
-  const float rvpr = 1.0f / (float)vpr;
-  auto row_of = [&](int i) {
-    int r = (int)((float)i * rvpr);
-    r -= r * vpr > i;
-    r += (r + 1) * vpr <= i;
-    return r;
-  };
-  for (int i0 = 0; i0 < qtotal; i0 += 8 * 256) {
-    uint4 qv[8];
+  uint4 qv[QPT];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = i0 + j * 256 + tid;
-      const int row = row_of(i);
-      qv[j] = (i < qtotal && row < p.C) ? *(const uint4*)(Qg + (size_t)row * row_bytes + 16 * (i - row * vpr))
-                                        : make_uint4(0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = i0 + j * 256 + tid;
-      const int row = row_of(i);
-      if (i < qtotal) *(uint4*)(smem + row * ldq + 16 * (i - row * vpr)) = qv[j];
-    }
+  for (int j = 0; j < QPT; ++j) {
+    const int i = j * 256 + tid;
+    const int row = i / VPR;
+    const bool ok = (QTOT % 256 == 0 || i < QTOT) && row < p.C;
+    qv[j] = *(const uint4*)(Qg + (ok ? (size_t)row * ROWB + 16 * (i - row * VPR) : 0));
   }
   uint4 buf[CH];
 #pragma unroll
@@ -255,6 +238,12 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     en_r[i] = p.en[mc];
     used_r[i] = p.used[mc];
   }
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) {
+    const int i = j * 256 + tid;
+    const int row = i / VPR;
+    if (QTOT % 256 == 0 || i < QTOT) *(uint4*)(smem + row * LDQ + 16 * (i - row * VPR)) = qv[j];
+  }
   __syncthreads();
   {
 #pragma unroll
@@ -262,7 +251,7 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
       const int kb = i * 64 + 16 * (lane >> 4);  // byte offset of this lane's k run
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const uint4 q = *(const uint4*)(smem + (t * 16 + (lane & 15)) * ldq + kb);
+        const uint4 q = *(const uint4*)(smem + (t * 16 + (lane & 15)) * LDQ + kb);
         if constexpr (BF16) {
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, buf[i]),
                                                           __builtin_bit_cast(bf16x8, q), acc[t], 0, 0, 0);
