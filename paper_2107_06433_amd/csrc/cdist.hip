@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) cdist_kernel(CdistParams p) {
       for (int i = 0; i < 4; ++i) {
         const int64_t m = m0 + wm * T::TM + a * 16 + 4 * (lane >> 4) + i;
         if (m >= p.U) continue;
-        float kv = 0.f;
+        float kv = 1.f;  // an unused query slot: K = 1 is the Sinkhorn kernels' padding
         if (q >= 0) {
           const float m2 = p.en[m] + qn - 2.f * acc[a][b][i];
           const float dist = p.used[m] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     for (int i = 0; i < 4; ++i) {
       const int64_t m = m0 + 4 * (lane >> 4) + i;
       if (m >= p.U) continue;
-      float kv = 0.f;
+      float kv = 1.f;  // an unused query slot (padding for the Sinkhorn kernels)
       if (q >= 0) {
         const float m2 = en_r[i] + qn - 2.f * acc[t][i];
         const float dist = used_r[i] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));

@@ -257,11 +257,12 @@ __device__ __forceinline__ float max_low(float x) {
 
 // The cost M of a kernel entry K = exp(-lambda M) is -ln(K) / lambda =
 // log2(K) * (-ln 2 / lambda).  The final pass sums K u log2(K) and applies the
-// constant once per document.  K = 1 (the same word) gives exactly 0; K is
-// clamped to the smallest normal float first, so an underflowed entry (or a
-// padding zero) adds K u * (-126) ~ 0 instead of 0 * inf.
+// constant once per document.  The smallest normal float is added first: it
+// leaves every K >= 2^-102 unchanged (K = 1, a padding entry, gives exactly
+// 0) and turns K = 0 (an underflowed entry) into K u * (-126) = 0 instead of
+// 0 * inf.  One add, where a clamp with fmaxf costs two instructions.
 __device__ __forceinline__ float log2_gibbs(float k) {
-  return __builtin_amdgcn_logf(fmaxf(k, 1.17549435e-38f));
+  return __builtin_amdgcn_logf(k + 1.17549435e-38f);
 }
 constexpr float kNegLn2 = -0.693147180559945309f;
 
@@ -296,11 +297,17 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     const int64_t beg = rec_begin(rec);
     const int n = rec.z, k = rec.w;
 
-    // ---- gather this lane's words of document k and their K^T entries.  A
-    // row slot with no word (or a zero weight) is padding: its K row is zero
-    // and column lane 0 seeds its dot product with 1, so w = 0 * rcp(1) = 0.
+    // ---- gather this lane's words of document k and their K^T entries.
+    // Padding -- a row slot with no word (or a zero weight), a column slot
+    // with no query word (r = 0: the cost-matrix kernel stores K = 1 there,
+    // and slots past S are set here) -- holds K = 1.  A
+    // padding row then has a positive dot product (the item's real u), so its
+    // w = 0 * rcp(.) = 0 and it adds nothing to any column; a padding column
+    // sums the item's w (> 0 for a document with mass), so its u =
+    // 0 * rcp(.) = 0 and it adds nothing to any row.  In the final pass
+    // log2(1) = 0.
     int wid[TR];
-    float cw[TR], rpad[TR];
+    float cw[TR];
     float K[TR][TC];
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
@@ -309,7 +316,6 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       const float c = j < n ? p.wn[beg + j] : 0.f;
       wid[t] = c > 0.f ? id : -1;
       cw[t] = c > 0.f ? c : 0.f;
-      rpad[t] = (wid[t] < 0 && cg == 0) ? 1.f : 0.f;
     }
     // Columns of lane cg: the 4-column chunks cg, cg + CG, ... (4 TC4 columns,
     // one 16-byte load per row each: S and every K^T row start are multiples
@@ -326,26 +332,23 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         const int c0 = col_of(4 * c);
         const float4 v = *(const float4*)(row + (c0 < S ? c0 : S - 4));  // clamped inside the row
         const bool ok = wid[t] >= 0 && c0 < S;
-        K[t][4 * c] = ok ? v.x : 0.f;
-        K[t][4 * c + 1] = ok ? v.y : 0.f;
-        K[t][4 * c + 2] = ok ? v.z : 0.f;
-        K[t][4 * c + 3] = ok ? v.w : 0.f;
+        K[t][4 * c] = ok ? v.x : 1.f;
+        K[t][4 * c + 1] = ok ? v.y : 1.f;
+        K[t][4 * c + 2] = ok ? v.z : 1.f;
+        K[t][4 * c + 3] = ok ? v.w : 1.f;
       }
 #pragma unroll
       for (int e = 4 * TC4; e < TC; ++e) {
         const int col = col_of(e);
         const float v = row[col < S ? col : S - 1];  // clamped: never reads past the row
-        K[t][e] = (wid[t] >= 0 && col < S) ? v : 0.f;
+        K[t][e] = (wid[t] >= 0 && col < S) ? v : 1.f;
       }
     }
-    // Column slots past the query's words are padding too: K is zero there
-    // and row lane 0 seeds their sum with 1, so u = 0 * rcp(1) = 0.
-    float rv[TC], u[TC], cpad[TC];
+    float rv[TC], u[TC];
 #pragma unroll
     for (int e = 0; e < TC; ++e) {
       const int col = col_of(e);
       rv[e] = col < S ? p.r[col] : 0.f;
-      cpad[e] = (rv[e] > 0.f || rs != 0) ? 0.f : 1.f;
       if (p.load_u)
         u[e] = (active && col < S) ? p.u[(size_t)k * S + col] : 0.f;
       else
@@ -366,6 +369,20 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     constexpr int LQ = LG_CG == 1 ? 1 : 2;
     float cqk[LowPack<LQ, TR>::P];
     if constexpr (ROWQ) pack_low<LQ, TR>(cw, cqk, lane);
+    // w_j = c_j / s_j for this lane's rows, from partial dot products s
+    // (summed over the column lanes here), in every column lane of the row
+    auto row_div = [&](float (&sp)[TR], float (&q)[TR]) {
+      if constexpr (ROWP) {
+        sum_low<4>(sp);
+        high_div<MR, TR>(cpk, sp, q);
+      } else if constexpr (ROWQ) {
+        low_div<LQ, LG_CG == 4>(cqk, sp, q, lane);
+      } else {
+        sum_low<LG_CG>(sp);
+#pragma unroll
+        for (int t = 0; t < TR; ++t) q[t] = fast_div(cw[t], sp[t]);
+      }
+    };
     float wv[TR];
     if (p.load_w) {
 #pragma unroll
@@ -382,21 +399,12 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         float s[TR];
 #pragma unroll
         for (int t = 0; t < TR; ++t) {
-          float a = rpad[t];
+          float a = 0.f;
 #pragma unroll
           for (int e = 0; e < TC; ++e) a = fmaf(K[t][e], u[e], a);
           s[t] = a;
         }
-        if constexpr (ROWP) {
-          sum_low<4>(s);
-          high_div<MR, TR>(cpk, s, wv);
-        } else if constexpr (ROWQ) {
-          low_div<LQ, LG_CG == 4>(cqk, s, wv, lane);
-        } else {
-          sum_low<LG_CG>(s);
-#pragma unroll
-          for (int t = 0; t < TR; ++t) wv[t] = fast_div(cw[t], s[t]);
-        }
+        row_div(s, wv);
         if (p.store_w) {
           if (cg == 0 && active) {
 #pragma unroll
@@ -411,7 +419,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       float acc[TC];
 #pragma unroll
       for (int e = 0; e < TC; ++e) {
-        float a = cpad[e];
+        float a = 0.f;
 #pragma unroll
         for (int t = 0; t < TR; ++t) a = fmaf(K[t][e], wv[t], a);
         acc[e] = a;
@@ -449,13 +457,14 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         for (int e = 0; e < TC; ++e) un[e] = fast_div(rv[e], acc[e]);
       }
       if (p.tol > 0.f) {
-        // "while x changes": x = 1/u, so |x_new - x| / x_new = |u - u_new| / u.
-        // Every lane of the item holds the same u, so the decision is uniform
-        // over the item's waves.
+        // x = 1/u, so the relative change |x_new - x| / x_new is
+        // |u - u_new| / u; padding columns (u = 0) are skipped.  Every lane of
+        // the item holds the same u, so the decision is uniform over the
+        // item's waves.
         float dm = 0.f;
 #pragma unroll
         for (int e = 0; e < TC; ++e) {
-          if (rv[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un[e]) * __builtin_amdgcn_rcpf(u[e]));
+          if (u[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un[e]) * __builtin_amdgcn_rcpf(u[e]));
           u[e] = un[e];
         }
         dm = max_low<LG_CG>(dm);
@@ -482,12 +491,15 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     }
 
     // ---- final pass: d_k = sum_j c_jk ((K.*M)_j . u) / (K_j . u), with the
-    // costs recovered from the K entries held in registers
+    // costs recovered from the K entries held in registers.  c_j / (K_j . u)
+    // is the w of the final u, divided as in an iteration; every lane then
+    // adds w_j times its own columns' share of (K.*M)_j . u, so one sum over
+    // all lanes gives d_k.
     if (p.do_final) {
-      float sa[TR], sb[TR];
+      float sa[TR], sb[TR], wf[TR];
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
-        float a = rpad[t], b = 0.f;
+        float a = 0.f, b = 0.f;
 #pragma unroll
         for (int e = 0; e < TC; ++e) {
           const float ku = K[t][e] * u[e];
@@ -497,12 +509,10 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         sa[t] = a;
         sb[t] = b;
       }
-      sum_low<LG_CG>(sa);
-      sum_low<LG_CG>(sb);
+      row_div(sa, wf);
       float part[1] = {0.f};
 #pragma unroll
-      for (int t = 0; t < TR; ++t) part[0] = fmaf(cw[t], fast_div(sb[t], sa[t]), part[0]);
-      part[0] = cg == 0 ? part[0] : 0.f;
+      for (int t = 0; t < TR; ++t) part[0] = fmaf(wf[t], sb[t], part[0]);
       sum_low<6>(part);
       float tot = part[0];
       if constexpr (MW) {

@@ -90,7 +90,7 @@ struct CdistParams {
 // One fused SDDMM-SpMM launch over the documents of one length bucket for one
 // query.  The same kernel runs every schedule; flags pick the variant.
 struct SinkParams {
-  const float* kt;        // K^T block of the query: U rows x S floats
+  const float* kt;        // K^T block of the query: U rows x S floats (1 in unused slots)
   const float* r;         // S slots of the normalised query histogram (0 = unused slot)
   const int* vr;          // device: number of used slots (0 = invalid query)
   const int4* drec;       // documents of the bucket: (first entry lo, hi, length, id)
