@@ -39,7 +39,10 @@ struct Tile {
   static constexpr int NA = BM * BK / VEC / 256;     // 16-byte loads per thread
   static constexpr int NB = BN * BK / VEC / 256;
   static constexpr int VPR = BK / VEC;               // 16-byte loads per row
-  static constexpr size_t LDS = (size_t)2 * (BM + BN) * LDK * ESZ;
+  static constexpr size_t STAGE = (size_t)2 * (BM + BN) * LDK * ESZ;  // double-buffered A and B
+  // then the epilogue's per-row (|e|^2, word id) and per-column (query word
+  // id, |q|^2, column base and width) data
+  static constexpr size_t LDS = STAGE + (size_t)BM * 8 + (size_t)BN * 16;
   static_assert(FM >= 1 && FN >= 1 && NA >= 1 && NB >= 1, "tile");
   static_assert(BM * BK % (VEC * 256) == 0 && BN * BK % (VEC * 256) == 0, "loads");
   static_assert(BK % (BF16 ? 32 : 16) == 0 && 64 % BK == 0, "k step");
@@ -98,8 +101,40 @@ __global__ void __launch_bounds__(256) cdist_kernel(CdistParams p) {
 #pragma unroll
     for (int b = 0; b < T::FN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // the epilogue's row and column data go to LDS, fetched ahead of the first
+  // stage (indices clamped; rows past U and columns past C are never stored)
+  float* s_en = (float*)(smem + T::STAGE);
+  int* s_used = (int*)(s_en + BM);
+  int2* s_ci = (int2*)(s_used + BM);
+  int* s_qid = (int*)(s_ci + BN);
+  float* s_qn = (float*)(s_qid + BN);
+  float e_en = 0.f, e_qn = 0.f;
+  int e_used = 0, e_qid = 0;
+  int2 e_ci = make_int2(0, 0);
+  if (tid < BM) {
+    const int64_t m = m0 + tid;
+    const int64_t mc = m < p.U ? m : p.U - 1;
+    e_en = p.en[mc];
+    e_used = p.used[mc];
+  }
+  if (tid < BN) {
+    const int64_t n = n0 + tid;
+    const int64_t nc = n < p.C ? n : p.C - 1;
+    e_qid = p.qid[nc];
+    e_qn = p.qn[nc];
+    e_ci = p.cinfo[nc];
+  }
   const int nk = p.dp / T::BK;
   load(0);
+  if (tid < BM) {
+    s_en[tid] = e_en;
+    s_used[tid] = e_used;
+  }
+  if (tid < BN) {
+    s_qid[tid] = e_qid;
+    s_qn[tid] = e_qn;
+    s_ci[tid] = e_ci;
+  }
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
@@ -149,29 +184,43 @@ __global__ void __launch_bounds__(256) cdist_kernel(CdistParams p) {
   }
 
   // Epilogue.  Accumulator register i of lane l holds row 4*(l/16)+i, column l%16
-  // of each 16x16 tile.
+  // of each 16x16 tile.  The row and column data come from LDS: a store
+  // counts against the same memory counter as a global load, so a global
+  // load consumed between two stores would wait for the first store.
+  int qc[T::FN];
+  float qnc[T::FN];
+  int2 cic[T::FN];
 #pragma unroll
   for (int b = 0; b < T::FN; ++b) {
-    const int64_t n = n0 + wn * T::TN + b * 16 + (lane & 15);
-    if (n >= p.C) continue;
-    const int q = p.qid[n];
-    const float qn = p.qn[n];
-    const int2 ci = p.cinfo[n];
-    float* kt = p.kt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
+    const int c = wn * T::TN + b * 16 + (lane & 15);
+    qc[b] = s_qid[c];
+    qnc[b] = s_qn[c];
+    cic[b] = s_ci[c];
+  }
 #pragma unroll
-    for (int a = 0; a < T::FM; ++a)
+  for (int a = 0; a < T::FM; ++a) {
+    float enr[4];
+    int usr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * T::TM + a * 16 + 4 * (lane >> 4) + i;
+      enr[i] = s_en[r];
+      usr[i] = s_used[r];
+    }
+#pragma unroll
+    for (int b = 0; b < T::FN; ++b) {
+      const int64_t n = n0 + wn * T::TN + b * 16 + (lane & 15);
+      float* kt = p.kt + (size_t)cic[b].x * (size_t)p.U + (n - cic[b].x);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t m = m0 + wm * T::TM + a * 16 + 4 * (lane >> 4) + i;
-        if (m >= p.U) continue;
-        float kv = 1.f;  // an unused query slot: K = 1 is the Sinkhorn kernels' padding
-        if (q >= 0) {
-          const float m2 = p.en[m] + qn - 2.f * acc[a][b][i];
-          const float dist = p.used[m] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
-          kv = expf(-p.lam * dist);
-        }
-        kt[(size_t)m * ci.y] = kv;
+        const float m2 = enr[i] + qnc[b] - 2.f * acc[a][b][i];
+        const float dist = usr[i] == qc[b] ? 0.f : sqrtf(fmaxf(m2, 0.f));
+        // an unused query slot holds K = 1: padding for the Sinkhorn kernels
+        const float kv = qc[b] >= 0 ? expf(-p.lam * dist) : 1.f;
+        if (n < p.C && m < p.U) kt[(size_t)m * cic[b].y] = kv;
       }
+    }
   }
 }
 
@@ -228,7 +277,8 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   uint4 buf[CH];
 #pragma unroll
   for (int i = 0; i < CH; ++i) buf[i] = *(const uint4*)(Ag + (size_t)i * 64);
-  // the epilogue's per-row data, fetched early for the same reason
+  // the epilogue's per-row and per-column data, fetched early for the same
+  // reason (indices clamped)
   float en_r[4];
   int used_r[4];
 #pragma unroll
@@ -237,6 +287,17 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     const int64_t mc = m < p.U ? m : p.U - 1;
     en_r[i] = p.en[mc];
     used_r[i] = p.used[mc];
+  }
+  int q_c[NT];
+  float qn_c[NT];
+  int2 ci_c[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int64_t n = t * 16 + (lane & 15);
+    const int64_t nc = n < p.C ? n : p.C - 1;
+    q_c[t] = p.qid[nc];
+    qn_c[t] = p.qn[nc];
+    ci_c[t] = p.cinfo[nc];
   }
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
@@ -264,26 +325,26 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
       }
     }
   }
-  // epilogue: register i of lane l holds row 4*(l/16)+i, column l%16 of each tile
+  // epilogue: register i of lane l holds row 4*(l/16)+i, column l%16 of each
+  // tile.  All K values first, then the stores (a store counts against the
+  // same memory counter as a load; nothing waits on them).
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float m2 = en_r[i] + qn_c[t] - 2.f * acc[t][i];
+      const float dist = used_r[i] == q_c[t] ? 0.f : sqrtf(fmaxf(m2, 0.f));
+      // an unused query slot holds K = 1: padding for the Sinkhorn kernels
+      acc[t][i] = q_c[t] >= 0 ? expf(-p.lam * dist) : 1.f;
+    }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int64_t n = t * 16 + (lane & 15);
-    if (n >= p.C) continue;
-    const int q = p.qid[n];
-    const float qn = p.qn[n];
-    const int2 ci = p.cinfo[n];
-    float* kt = p.kt + (size_t)ci.x * (size_t)p.U + (n - ci.x);
+    float* kt = p.kt + (size_t)ci_c[t].x * (size_t)p.U + (n - ci_c[t].x);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t m = m0 + 4 * (lane >> 4) + i;
-      if (m >= p.U) continue;
-      float kv = 1.f;  // an unused query slot (padding for the Sinkhorn kernels)
-      if (q >= 0) {
-        const float m2 = en_r[i] + qn - 2.f * acc[t][i];
-        const float dist = used_r[i] == q ? 0.f : sqrtf(fmaxf(m2, 0.f));
-        kv = expf(-p.lam * dist);
-      }
-      kt[(size_t)m * ci.y] = kv;
+      if (n < p.C && m < p.U) kt[(size_t)m * ci_c[t].y] = acc[t][i];
     }
   }
 }
