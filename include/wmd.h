@@ -142,7 +142,7 @@ typedef struct {
   float tol;                  /* 0: exactly max_iter iterations (the paper's cut-off).
                                  > 0: a document stops as soon as an iteration changes
                                  its x by at most tol, max_i |x_new_i - x_i| / x_new_i
-                                 <= tol ("while x changes", Algorithm 1), and at
+                                 <= tol (Algorithm 1 loops until x stops changing), and at
                                  max_iter at the latest.  Resident schedule only.       */
   int32_t* iters;             /* device, B*N int32 or NULL: iterations each document ran */
   int32_t flags;              /* WMD_QUERY_* bits                                       */

@@ -14,7 +14,7 @@ Readings of points the paper leaves open (each is listed in the design doc):
   form; Table I calls ``cdist`` with its default metric);
 * ``K = exp(-lambda M)`` with ``lambda > 0`` (Algorithm 1; the prose of
   Section III-B-1 passes a negated lambda, which is the same thing);
-* the "while x changes" loop runs exactly ``max_iter`` times (the cut-off of
+* the loop that repeats until x stops changing runs exactly ``max_iter`` times (the cut-off of
   Section III-B-1); the final u, v update follows it;
 * ``k^T`` in the update of Algorithm 1 is ``K^T``;
 * duplicate query words are summed (``r`` is a histogram over the vocabulary),
@@ -117,7 +117,7 @@ def sinkhorn_scalings(r, M, c, lam: float, max_iter: int):
 
 
 def sinkhorn_scalings_until(r, M, c, lam: float, max_iter: int, tol: float):
-    """Algorithm 1 with its "while x changes" loop for one document column.
+    """Algorithm 1 with its loop until x stops changing, for one document column.
 
     Iterates as ``sinkhorn_scalings`` but stops after the first iteration whose
     relative change of x, max_i |x_new_i - x_i| / x_new_i, is at most ``tol``

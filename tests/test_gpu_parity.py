@@ -385,7 +385,7 @@ def test_corpus_validation_errors(W):
         W.Corpus.from_numpy(long.emb, long.doc_ptr, long.word_ids, long.weights)
 
 
-# ------------------------------------------------------- "while x changes" stop
+# ------------------------------------------------------- stop once x settles
 
 @pytest.mark.parametrize("tol", [1e-2, 1e-4])
 def test_tolerance_stop_counts_and_values(W, single, tol):

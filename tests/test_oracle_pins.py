@@ -337,7 +337,7 @@ def test_one_iteration_closed_form(seed):
     assert abs(one_doc(E, q, qw, ids, w, lam, 1) - want) <= 1e-13 * want
 
 
-# --- the "while x changes" stop --------------------------------------------------------
+# --- the stop once x settles ---------------------------------------------------------------
 
 def test_tolerance_stop_consistency():
     """tol = 0 runs every iteration; a huge tol stops after one; the count
