@@ -170,9 +170,10 @@ __device__ __forceinline__ void high_div(const float (&np)[HighPack<M, N>::P], c
 
 // The same idea inside a lane quad, with DPP: x[e] / (sum over lane bit 0
 // (L = 1) or bits 0 and 1 (L = 2) of den[e]), optionally also summed over
-// lane bits 2 and 3 (HI23).  Lane q of a quad ends up with the total of
-// element 4i + q (or 2i + (q & 1)), divides once, and quad broadcasts give
-// every lane all the quotients.
+// lane bits 2 and 3 (HI23) and then over bit 4 (HB >= 1) and bit 5 (HB = 2)
+// with permlane swaps.  Lane q of a quad ends up with the total of element
+// 4i + q (or 2i + (q & 1)), divides once, and quad broadcasts give every lane
+// all the quotients.
 template <int L, int N>
 struct LowPack {
   static constexpr int NQ = L == 2 ? N / 4 : 0;
@@ -196,7 +197,7 @@ __device__ __forceinline__ void pack_low(const float (&x)[N], float (&xp)[LowPac
   if constexpr (H::N1 > 0) xp[H::NQ + H::NP] = x[N - 1];
 }
 
-template <int L, bool HI23, int N>
+template <int L, bool HI23, int HB, int N>
 __device__ __forceinline__ void low_div(const float (&np)[LowPack<L, N>::P], const float (&den)[N], float (&out)[N],
                                         int lane) {
   using H = LowPack<L, N>;
@@ -213,6 +214,8 @@ __device__ __forceinline__ void low_div(const float (&np)[LowPack<L, N>::P], con
       z += dpp<kDppRor8>(z);
       z += dpp<kDppRor4>(z);
     }
+    if constexpr (HB > 0) z = add_xor16(z);
+    if constexpr (HB > 1) z = add_xor32(z);
     return z;
   };
 #pragma unroll
@@ -354,29 +357,25 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       else
         u[e] = rv[e] > 0.f ? (float)vr : 0.f;  // x = 1/v_r
     }
-    // Reductions that cross the permlane bits (lane bits 4 and 5) divide in
-    // packed form: rows when the column lanes reach bit 4 (lg_cg >= 5), columns
-    // of one-wave items when the row lanes do (lg_cg <= 5).
-    constexpr bool ROWP = LG_CG >= 5;
+    // Column sums that cross the permlane bits (lane bits 4 and 5) divide in
+    // packed form when the row lanes reach them (one-wave items, lg_cg <= 5).
     constexpr bool COLP = !MW && LG_CG <= 5;
-    constexpr int MR = LG_CG == 5 ? 1 : 3;
     constexpr int MC = LG_CG <= 4 ? 3 : 2;
-    float cpk[HighPack<MR, TR>::P], rpk[HighPack<MC, TC>::P];
-    if constexpr (ROWP) pack_high<MR, TR>(cw, cpk, lane);
+    float rpk[HighPack<MC, TC>::P];
     if constexpr (COLP) pack_high<MC, TC>(rv, rpk, lane);
-    // rows over 2 or 16 column lanes (lg_cg 1, 2 or 4) divide packed within quads
-    constexpr bool ROWQ = LG_CG == 1 || LG_CG == 2 || LG_CG == 4;
+    // Row sums over 2, 4, 16, 32 or 64 column lanes divide packed within
+    // quads (lane bits 0 and 1), the quads' totals summed over the remaining
+    // column-lane bits first; 8 column lanes (lg_cg 3) sum each row plainly.
+    constexpr bool ROWQ = LG_CG != 0 && LG_CG != 3;
     constexpr int LQ = LG_CG == 1 ? 1 : 2;
+    constexpr int RHB = LG_CG > 4 ? LG_CG - 4 : 0;
     float cqk[LowPack<LQ, TR>::P];
     if constexpr (ROWQ) pack_low<LQ, TR>(cw, cqk, lane);
     // w_j = c_j / s_j for this lane's rows, from partial dot products s
     // (summed over the column lanes here), in every column lane of the row
     auto row_div = [&](float (&sp)[TR], float (&q)[TR]) {
-      if constexpr (ROWP) {
-        sum_low<4>(sp);
-        high_div<MR, TR>(cpk, sp, q);
-      } else if constexpr (ROWQ) {
-        low_div<LQ, LG_CG == 4>(cqk, sp, q, lane);
+      if constexpr (ROWQ) {
+        low_div<LQ, (LG_CG >= 4), RHB>(cqk, sp, q, lane);
       } else {
         sum_low<LG_CG>(sp);
 #pragma unroll
