@@ -273,6 +273,30 @@ def test_empty_zero_weight_and_duplicate_entries(W):
     assert_close(got, ref, TOL32, "edge docs")
 
 
+def test_short_and_long_query_selection_agree(W):
+    """Queries of at most 64 entries are selected by one wave, longer ones by
+    the block-wide path.  The same words, with repeats and zero weights, padded
+    past 64 entries with more zero weights, give the same distances (to the
+    rounding of a different slot width) and both match the oracle."""
+    rng = np.random.default_rng(46)
+    c = handmade_corpus(rng, 400, 24, rng.integers(1, 40, size=60))
+    base_ids = rng.choice(400, size=30, replace=False)
+    ids_a = np.concatenate([base_ids, base_ids[:6], rng.choice(400, size=4)]).astype(np.int32)
+    w_a = rng.integers(0, 4, size=len(ids_a)).astype(np.float32)
+    w_a[:3] = [1, 2, 3]
+    pad = rng.choice(400, size=70 - len(ids_a)).astype(np.int32)
+    ids_b = np.concatenate([ids_a, pad])
+    w_b = np.concatenate([w_a, np.zeros(len(pad), np.float32)])
+    assert len(ids_a) <= 64 < len(ids_b)
+    q = synth.Queries(q_ptr=np.array([0, len(ids_a), len(ids_a) + len(ids_b)]),
+                      ids=np.concatenate([ids_a, ids_b]), weights=np.concatenate([w_a, w_b]))
+    got = run(W, corpus_of(W, c), q, 10.0, 15)
+    ref = oracle_support(c, ids_a, w_a, 10.0, 15)
+    assert_close(got[0], ref, TOL32, "short query")
+    assert_close(got[1], ref, TOL32, "long query")
+    assert_close(got[1], got[0], 1e-5, "short vs long selection")
+
+
 def test_all_length_buckets_and_multiwave_items(W):
     rng = np.random.default_rng(42)
     lengths = [1, 2, 15, 16, 17, 33, 64, 65, 127, 128, 200, 256, 257, 511, 700, 1024, 1500, 2048, 3000, 4096]
