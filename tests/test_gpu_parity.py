@@ -5,7 +5,9 @@ oracle; bf16 cost-matrix GEMM within 1e-3; both as |g - o| <= tol |o| + 1e-7
 (the absolute floor only matters for identical documents, whose distance is
 near zero).  Integer outputs (error codes) and NaN placement are exact.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -151,6 +153,29 @@ def test_single_bf16_sampled(W, single, single_run):
     ids, qw = single.queries.query(0)
     ref = oracle_support(single.corpus, ids, qw, single.lam, single.max_iter, docs)
     assert_close(g16[docs], ref, TOL16, "single bf16")
+
+
+def test_single_error_distribution(W, single, single_run):
+    """Relative WMD error of every document of the single-query workload
+    against the FP64 oracle, for the f32 and the bf16 cost-matrix inputs
+    (max, median and 99th percentile are printed; with WMD_REPORT_DIR set they
+    are also written there as JSON)."""
+    _, g32, g16 = single_run
+    ids, qw = single.queries.query(0)
+    ref = oracle_support(single.corpus, ids, qw, single.lam, single.max_iter)
+    ok = ~np.isnan(ref)
+    report = {"docs": int(ok.sum())}
+    for name, g, tol in (("fp32", g32, TOL32), ("bf16", g16, TOL16)):
+        e = np.abs(g[ok].astype(np.float64) - ref[ok]) / np.abs(ref[ok])
+        report[name] = {"max_rel": float(e.max()), "median_rel": float(np.median(e)),
+                        "p99_rel": float(np.quantile(e, 0.99)), "tolerance": tol}
+        assert_close(g, ref, tol, f"single {name}, every document")
+    print("single-query WMD error vs FP64 oracle:", json.dumps(report))
+    out = os.environ.get("WMD_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_single.json"), "w") as f:
+            json.dump(report, f, indent=1)
 
 
 def test_single_every_document_within_cost_range(W, single, single_run):
