@@ -274,9 +274,14 @@ __device__ __forceinline__ int64_t rec_begin(const int4& r) {
 }
 
 // One launch group's share of the work: block `blk` of `nblk` blocks walks
-// the items blk, blk + nblk, ... of p's documents.
-template <int TC, int TR, int LG_CG, int MAXW>
+// the items blk, blk + nblk, ... of p's documents.  RES: the resident
+// schedule only (u and w neither loaded nor stored, every iteration and the
+// final pass in this launch), so the code for the other schedules and the
+// registers it needs are left out.
+template <int TC, int TR, int LG_CG, int MAXW, bool RES>
 __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk) {
+  const bool load_u = !RES && p.load_u, store_u = !RES && p.store_u;
+  const bool load_w = !RES && p.load_w, store_w = !RES && p.store_w;
   constexpr bool MW = MAXW > 1;                   // an item spans several waves of one block
   constexpr int CG = 1 << LG_CG;
   constexpr int RSW = 64 >> LG_CG;                // row lanes per wave
@@ -352,7 +357,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     for (int e = 0; e < TC; ++e) {
       const int col = col_of(e);
       rv[e] = col < S ? p.r[col] : 0.f;
-      if (p.load_u)
+      if (load_u)
         u[e] = (active && col < S) ? p.u[(size_t)k * S + col] : 0.f;
       else
         u[e] = rv[e] > 0.f ? (float)vr : 0.f;  // x = 1/v_r
@@ -383,7 +388,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       }
     };
     float wv[TR];
-    if (p.load_w) {
+    if (load_w) {
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
         const int j = rs + RS * t;
@@ -394,7 +399,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     // ---- Sinkhorn-Knopp iterations
     int ran = p.iters;
     for (int it = 0; it < p.iters; ++it) {
-      if (!p.load_w) {
+      if (!load_w) {
         float s[TR];
 #pragma unroll
         for (int t = 0; t < TR; ++t) {
@@ -404,7 +409,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
           s[t] = a;
         }
         row_div(s, wv);
-        if (p.store_w) {
+        if (store_w) {
           if (cg == 0 && active) {
 #pragma unroll
             for (int t = 0; t < TR; ++t) {
@@ -481,7 +486,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       for (int e = 0; e < TC; ++e) u[e] = un[e];
     }
 
-    if (p.store_u && rs == 0 && active) {
+    if (store_u && rs == 0 && active) {
 #pragma unroll
       for (int e = 0; e < TC; ++e) {
         const int col = col_of(e);
@@ -533,9 +538,9 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
 }
 
 // Multi-wave items: one item per block of up to MAXW waves.
-template <int TC, int TR, int LG_CG, int MAXW>
+template <int TC, int TR, int LG_CG, int MAXW, bool RES>
 __global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
-  sink_body<TC, TR, LG_CG, MAXW>(p, blockIdx.x, gridDim.x);
+  sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x);
 }
 
 // One-wave items, four per block, for several length buckets of one query in
@@ -544,7 +549,7 @@ __global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
 // (body 0), TRMAX/2 (body 1) or TRMAX/4 (body 2), enough for its bucket.
 // Groups come longest documents first, so the longest items start first and
 // the short ones fill in behind them.  The other fields of p are shared.
-template <int TC, int TRMAX, int LG_CG>
+template <int TC, int TRMAX, int LG_CG, bool RES>
 __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
   const int b = blockIdx.x;
   int g = 0, b0 = 0;
@@ -567,12 +572,12 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
   p.drec += off;
   p.ndocs = nd;
   if (body == 0) {
-    sink_body<TC, TRMAX, LG_CG, 1>(p, b - b0, b1 - b0);
+    sink_body<TC, TRMAX, LG_CG, 1, RES>(p, b - b0, b1 - b0);
   } else if constexpr (TRMAX >= 2) {
     if (body == 1) {
-      sink_body<TC, TRMAX / 2, LG_CG, 1>(p, b - b0, b1 - b0);
+      sink_body<TC, TRMAX / 2, LG_CG, 1, RES>(p, b - b0, b1 - b0);
     } else if constexpr (TRMAX >= 4) {
-      sink_body<TC, TRMAX / 4, LG_CG, 1>(p, b - b0, b1 - b0);
+      sink_body<TC, TRMAX / 4, LG_CG, 1, RES>(p, b - b0, b1 - b0);
     }
   }
 }
@@ -580,7 +585,8 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
 struct SinkEntry {
   int tc, tr, lg_cg;
   int maxw;       // 1: one wave per item (sink_merge_kernel, TRMAX = tr); 4, 8 or 16: waves per block at most
-  const void* fn;
+  const void* fn;        // resident schedule only
+  const void* fn_sched;  // every schedule (u / w loaded and stored as the launch says)
 };
 
 // Register budget per lane of the K^T block: up to 128 cells in blocks of at
@@ -595,15 +601,17 @@ constexpr bool kSinkFits = TC * TR <= (MAXW == 16 ? 64 : 128);
 
 template <int TC, int TR, int LG_CG, int MAXW, bool OK = kSinkFits<TC, TR, MAXW>>
 struct SinkPick {
-  static SinkEntry get() { return SinkEntry{TC, TR, LG_CG, MAXW, nullptr}; }
+  static SinkEntry get() { return SinkEntry{TC, TR, LG_CG, MAXW, nullptr, nullptr}; }
 };
 template <int TC, int TR, int LG_CG, int MAXW>
 struct SinkPick<TC, TR, LG_CG, MAXW, true> {
   static SinkEntry get() {
     if constexpr (MAXW == 1)
-      return SinkEntry{TC, TR, LG_CG, MAXW, (const void*)sink_merge_kernel<TC, TR, LG_CG>};
+      return SinkEntry{TC, TR, LG_CG, MAXW, (const void*)sink_merge_kernel<TC, TR, LG_CG, true>,
+                       (const void*)sink_merge_kernel<TC, TR, LG_CG, false>};
     else
-      return SinkEntry{TC, TR, LG_CG, MAXW, (const void*)sink_kernel<TC, TR, LG_CG, MAXW>};
+      return SinkEntry{TC, TR, LG_CG, MAXW, (const void*)sink_kernel<TC, TR, LG_CG, MAXW, true>,
+                       (const void*)sink_kernel<TC, TR, LG_CG, MAXW, false>};
   }
 };
 

@@ -114,6 +114,9 @@ __global__ void __launch_bounds__(256) sink_stream_kernel(SinkParams p) {
   }
 }
 
+// regs and spills are those of the resident-only variant: shapes are chosen
+// for the resident schedule, and the other schedules (comparison baselines)
+// run the general variant of the same shape.
 struct Shape {
   SinkEntry e;
   int regs;      // VGPRs per lane of the compiled kernel
@@ -143,6 +146,13 @@ const std::vector<Shape>& shapes() {
     }
   });
   return all;
+}
+
+// The compiled variant for a launch: the resident-only one when the launch
+// neither loads nor stores u or w.
+const void* kernel_for(const Shape& sh, const SinkParams& p) {
+  const bool resident = !p.load_u && !p.store_u && !p.load_w && !p.store_w;
+  return resident ? sh.e.fn : sh.e.fn_sched;
 }
 
 const Shape* find_shape(const SinkConfig& c) {
@@ -276,11 +286,11 @@ hipError_t launch_sink(const SinkParams& p, const SinkConfig& c, int grid, hipSt
     m.end[0] = grid;
     m.ndocs[0] = p.ndocs;
     void* args[] = {&m};
-    return hipLaunchKernel(sh->e.fn, dim3(grid), dim3(256), args, 0, s);
+    return hipLaunchKernel(kernel_for(*sh, p), dim3(grid), dim3(256), args, 0, s);
   }
   SinkParams a = p;
   void* args[] = {&a};
-  return hipLaunchKernel(sh->e.fn, dim3(grid), dim3(sink_block(c)), args, lds_bytes(c), s);
+  return hipLaunchKernel(kernel_for(*sh, p), dim3(grid), dim3(sink_block(c)), args, lds_bytes(c), s);
 }
 
 namespace {
@@ -398,7 +408,7 @@ hipError_t launch_sink_merged(const SinkParams& p, const MergePlan& plan, const 
   *grid_out = grid;
   if (grid == 0) return hipSuccess;
   void* args[] = {&m};
-  return hipLaunchKernel(sh->e.fn, dim3(grid), dim3(256), args, 0, s);
+  return hipLaunchKernel(kernel_for(*sh, p), dim3(grid), dim3(256), args, 0, s);
 }
 
 }  // namespace wmd
