@@ -134,13 +134,27 @@ __device__ __forceinline__ void pack_high(const float (&x)[N], float (&xp)[HighP
   if constexpr (H::N1 > 0) xp[H::NQ + H::NP] = x[N - 1];
 }
 
-template <int M, int N>
+// LO < 4: the sums also run over lane bits [LO, 4), added with DPP after the
+// packing, so once per register instead of once per element (every 16-lane
+// row holds one element then, and row_ror / quad_perm keep the bits below LO
+// apart).
+template <int LO>
+__device__ __forceinline__ float sum_row_bits(float z) {
+  if constexpr (LO <= 3) z += dpp<kDppRor8>(z);
+  if constexpr (LO <= 2) z += dpp<kDppRor4>(z);
+  if constexpr (LO <= 1) z += dpp<kDppXor2>(z);
+  if constexpr (LO <= 0) z += dpp<kDppXor1>(z);
+  return z;
+}
+
+template <int M, int N, int LO = 4>
 __device__ __forceinline__ void high_div(const float (&np)[HighPack<M, N>::P], const float (&den)[N], float (&out)[N]) {
   using H = HighPack<M, N>;
 #pragma unroll
   for (int q = 0; q < H::NQ; ++q) {
     const int a = 4 * q;
-    const float z = sum_scatter32(sum_scatter16(den[a], den[a + 1]), sum_scatter16(den[a + 2], den[a + 3]));
+    const float z = sum_row_bits<LO>(
+        sum_scatter32(sum_scatter16(den[a], den[a + 1]), sum_scatter16(den[a + 2], den[a + 3])));
     const float v = fast_div(np[q], z);
     float lo, hi;
     gather32(v, lo, hi);
@@ -151,17 +165,17 @@ __device__ __forceinline__ void high_div(const float (&np)[HighPack<M, N>::P], c
   for (int i = 0; i < H::NP; ++i) {
     const int a = 4 * H::NQ + 2 * i;
     if constexpr (M == 2) {
-      const float v = fast_div(np[H::NQ + i], sum_scatter32(den[a], den[a + 1]));
+      const float v = fast_div(np[H::NQ + i], sum_row_bits<LO>(sum_scatter32(den[a], den[a + 1])));
       gather32(v, out[a], out[a + 1]);
     } else {
       float z = sum_scatter16(den[a], den[a + 1]);
       if constexpr (M == 3) z = add_xor32(z);
-      const float v = fast_div(np[H::NQ + i], z);
+      const float v = fast_div(np[H::NQ + i], sum_row_bits<LO>(z));
       gather16(v, out[a], out[a + 1]);
     }
   }
   if constexpr (H::N1 > 0) {
-    float z = den[N - 1];
+    float z = sum_row_bits<LO>(den[N - 1]);
     if constexpr (M & 1) z = add_xor16(z);
     if constexpr (M & 2) z = add_xor32(z);
     out[N - 1] = fast_div(np[H::NQ + H::NP], z);
@@ -430,8 +444,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       }
       float un[TC];
       if constexpr (COLP) {
-        sum_high<LG_CG, TC, false>(acc);
-        high_div<MC, TC>(rpk, acc, un);
+        high_div<MC, TC, LG_CG>(rpk, acc, un);
       } else {
         sum_high<LG_CG>(acc);
         if constexpr (MW) {
