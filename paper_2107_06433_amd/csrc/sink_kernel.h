@@ -446,7 +446,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       if constexpr (COLP) {
         high_div<MC, TC, LG_CG>(rpk, acc, un);
       } else {
-        sum_high<LG_CG, TC, !MW>(acc);
+        if constexpr (!MW) sum_high<LG_CG>(acc);
         if constexpr (MW) {
           // cross-wave sum in two phases: every wave posts its column partials,
           // one thread per column adds them in wave order, every lane reads back
@@ -454,7 +454,8 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
           // barriers per iteration suffice.  (Measured faster than one barrier
           // with every lane adding all waves' partials of its columns, even
           // for 4 waves.)  The in-wave sum over row-lane bits 4 and 5 is a
-          // reduce-scatter: each 16-lane group (half) posts a different column.
+          // reduce-scatter: each 16-lane group (half) posts a different column,
+          // and the row-lane bits below 4 are added after the packing.
           float* part = lds + (it & 1) * nwaves * cw_stride;
           float* tot = lds + 2 * nwaves * cw_stride + (it & 1) * cw_stride;
           float* wp = part + wave * cw_stride + cg;
@@ -462,29 +463,47 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
           if constexpr (MB == 0) {
 #pragma unroll
             for (int e = 0; e < TC; ++e) wp[CG * e] = acc[e];
-          } else if ((lane & 15) < CG) {  // lanes whose in-row row-lane bits are 0
+          } else {
+            // every lane takes part in the cross-lane sums (DPP reads of a
+            // disabled lane are not defined to give its value); only lanes
+            // whose in-row row-lane bits are 0 post
             using H = HighPack<MB, TC>;
             const int G = (lane >> 4) & 3, half = lane >> 5;
+            const bool poster = (lane & 15) < CG;
+            float z[H::P];
 #pragma unroll
             for (int q = 0; q < H::NQ; ++q) {
               const int a = 4 * q;
-              wp[CG * (a + G)] = sum_scatter32(sum_scatter16(acc[a], acc[a + 1]), sum_scatter16(acc[a + 2], acc[a + 3]));
+              z[q] = sum_row_bits<LG_CG>(
+                  sum_scatter32(sum_scatter16(acc[a], acc[a + 1]), sum_scatter16(acc[a + 2], acc[a + 3])));
             }
 #pragma unroll
             for (int i = 0; i < H::NP; ++i) {
               const int a = 4 * H::NQ + 2 * i;
-              if constexpr (MB == 2) {
-                wp[CG * (a + half)] = sum_scatter32(acc[a], acc[a + 1]);
-              } else {
-                const float z = add_xor32(sum_scatter16(acc[a], acc[a + 1]));
-                if (G < 2) wp[CG * (a + G)] = z;
-              }
+              if constexpr (MB == 2)
+                z[H::NQ + i] = sum_row_bits<LG_CG>(sum_scatter32(acc[a], acc[a + 1]));
+              else
+                z[H::NQ + i] = sum_row_bits<LG_CG>(add_xor32(sum_scatter16(acc[a], acc[a + 1])));
             }
             if constexpr (H::N1 > 0) {
-              float z = acc[TC - 1];
-              if constexpr (MB & 1) z = add_xor16(z);
-              z = add_xor32(z);
-              if (MB == 2 ? half == 0 : G == 0) wp[CG * (TC - 1)] = z;
+              float y = sum_row_bits<LG_CG>(acc[TC - 1]);
+              if constexpr (MB & 1) y = add_xor16(y);
+              z[H::P - 1] = add_xor32(y);
+            }
+            if (poster) {
+#pragma unroll
+              for (int q = 0; q < H::NQ; ++q) wp[CG * (4 * q + G)] = z[q];
+#pragma unroll
+              for (int i = 0; i < H::NP; ++i) {
+                const int a = 4 * H::NQ + 2 * i;
+                if constexpr (MB == 2)
+                  wp[CG * (a + half)] = z[H::NQ + i];
+                else if (G < 2)
+                  wp[CG * (a + G)] = z[H::NQ + i];
+              }
+              if constexpr (H::N1 > 0) {
+                if (MB == 2 ? half == 0 : G == 0) wp[CG * (TC - 1)] = z[H::P - 1];
+              }
             }
           }
           __syncthreads();
