@@ -311,6 +311,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
   constexpr int cw_stride = CG * TC;              // LDS floats per wave and buffer
   const int S = p.S;
   const int vr = *p.vr;
+  float* rvs = lds + 2 * nwaves * cw_stride + 2 * cw_stride;  // multi-wave items only
 
   for (int base = blk * items; base < p.ndocs; base += nblk * items) {
     const int item = base + slot;
@@ -375,6 +376,15 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         u[e] = (active && col < S) ? p.u[(size_t)k * S + col] : 0.f;
       else
         u[e] = rv[e] > 0.f ? (float)vr : 0.f;  // x = 1/v_r
+    }
+    // multi-wave items: r of every (column lane, column) for the column
+    // threads; the same for every item of the launch, written before the
+    // first item's first barrier
+    if constexpr (MW) {
+      if (base == blk * items && wave == 0 && lane < CG) {
+#pragma unroll
+        for (int e = 0; e < TC; ++e) rvs[cg + CG * e] = rv[e];
+      }
     }
     // Column sums that cross the permlane bits (lane bits 4 and 5) divide in
     // packed form when the row lanes reach them (one-wave items, lg_cg <= 5).
@@ -507,17 +517,23 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
             }
           }
           __syncthreads();
+          // the column thread adds the waves' partials (all loads in flight
+          // together) and divides: r over the total, once per column instead
+          // of in every lane
           for (int c = threadIdx.x; c < cw_stride; c += blockDim.x) {
             float a = 0.f;
-            for (int w = 0; w < nwaves; ++w) a += part[w * cw_stride + c];
-            tot[c] = a;
+#pragma unroll
+            for (int w = 0; w < MAXW; ++w)
+              if (w < nwaves) a += part[w * cw_stride + c];
+            tot[c] = fast_div(rvs[c], a);
           }
           __syncthreads();
 #pragma unroll
-          for (int e = 0; e < TC; ++e) acc[e] = tot[cg + CG * e];
-        }
+          for (int e = 0; e < TC; ++e) un[e] = tot[cg + CG * e];
+        } else {
 #pragma unroll
-        for (int e = 0; e < TC; ++e) un[e] = fast_div(rv[e], acc[e]);
+          for (int e = 0; e < TC; ++e) un[e] = fast_div(rv[e], acc[e]);
+        }
       }
       if (p.tol > 0.f) {
         // x = 1/u, so the relative change |x_new - x| / x_new is

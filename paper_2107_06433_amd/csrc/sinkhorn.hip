@@ -161,11 +161,12 @@ const Shape* find_shape(const SinkConfig& c) {
   return nullptr;
 }
 
-// Multi-wave items: per-wave column partials and column totals, both doubled
-// for the alternation by iteration parity.
+// Multi-wave items: per-wave column partials and column results, both
+// doubled for the alternation by iteration parity, and r per column.
 size_t lds_bytes(const SinkConfig& c) {
   const size_t cols = (size_t)(1 << c.lg_cg) * c.tc;
-  return c.multiwave ? sizeof(float) * (2 * c.nwaves * cols + 2 * cols) : 0;
+  // two parity buffers of per-wave column partials, two of column results, r
+  return c.multiwave ? sizeof(float) * (2 * c.nwaves * cols + 3 * cols) : 0;
 }
 
 }  // namespace
