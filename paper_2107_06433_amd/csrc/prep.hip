@@ -95,15 +95,10 @@ __global__ void prep_emb_kernel(const float* emb, int d, int dp, const int* used
 // mirror patterns pair lanes holding equal partial sums), then the permlane
 // swaps across rows.
 __device__ __forceinline__ double sum_wave_f64(double x) {
-  auto step = [&](auto mov) {
-    const uint64_t u = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = mov((uint32_t)u), hi = mov((uint32_t)(u >> 32));
-    x += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-  };
-  step([](uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppXor1, 0xF, 0xF, true); });
-  step([](uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppXor2, 0xF, 0xF, true); });
-  step([](uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppHalfMirror, 0xF, 0xF, true); });
-  step([](uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppMirror, 0xF, 0xF, true); });
+  x += dpp_f64<kDppXor1>(x);
+  x += dpp_f64<kDppXor2>(x);
+  x += dpp_f64<kDppHalfMirror>(x);
+  x += dpp_f64<kDppMirror>(x);
   auto cross = [&](bool half) {
     const uint64_t u = (uint64_t)__double_as_longlong(x);
     const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);

@@ -48,11 +48,20 @@ __device__ __forceinline__ double query_row(const float* emb, int d, int dp, int
   return nrm;
 }
 
-// the 8 lanes' partial norms, added in a fixed order
+// the 8 lanes' partial norms, added in a fixed order: partners at lane
+// distance 1 and 2, then the other quad of the 8 (row_half_mirror pairs the
+// quads once each holds its sum), by DPP moves of both halves
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 __device__ __forceinline__ double sum_row_lanes(double x) {
-  x += __shfl_xor(x, 1, 8);
-  x += __shfl_xor(x, 2, 8);
-  x += __shfl_xor(x, 4, 8);
+  x += dpp_f64<kDppXor1>(x);
+  x += dpp_f64<kDppXor2>(x);
+  x += dpp_f64<kDppHalfMirror>(x);
   return x;
 }
 
