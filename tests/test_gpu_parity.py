@@ -337,6 +337,30 @@ def test_all_length_buckets_and_multiwave_items(W):
         assert_close(got[b], ref, TOL32, f"query width {len(ids)}")
 
 
+def test_schedules_agree_on_multiwave_items(W):
+    """Long documents and wide queries run as items of several waves (column
+    sums exchanged through LDS); the per-iteration and unfused schedules, which
+    keep u and w in memory between launches, compute what the resident one
+    does, and all match the oracle."""
+    rng = np.random.default_rng(47)
+    lengths = np.concatenate([rng.integers(150, 700, size=24), rng.integers(700, 1500, size=6)])
+    c = handmade_corpus(rng, 5000, 40, lengths)
+    qs = [rng.choice(5000, size=v, replace=False) for v in (70, 150)]
+    q = synth.Queries(q_ptr=np.concatenate([[0], np.cumsum([len(x) for x in qs])]),
+                      ids=np.concatenate(qs).astype(np.int32),
+                      weights=rng.integers(1, 4, size=sum(len(x) for x in qs)).astype(np.float32))
+    corpus = corpus_of(W, c)
+    res = run(W, corpus, q, 10.0, 15)
+    per = run(W, corpus, q, 10.0, 15, schedule="per_iteration")
+    unf = run(W, corpus, q, 10.0, 15, schedule="unfused")
+    for b in range(q.B):
+        ids, qw = q.query(b)
+        ref = oracle_support(c, ids, qw, 10.0, 15)
+        assert_close(res[b], ref, TOL32, f"resident, query width {len(ids)}")
+        assert_close(per[b], res[b], 1e-6, f"per-iteration vs resident, width {len(ids)}")
+        assert_close(unf[b], res[b], 1e-6, f"unfused vs resident, width {len(ids)}")
+
+
 def test_merged_launches_match_separate_launches(W):
     """One launch over several length buckets computes what one launch per
     bucket computes.  A short bucket may run with more rows per lane in the
