@@ -291,23 +291,27 @@ __device__ __forceinline__ int64_t rec_begin(const int4& r) {
 // the items blk, blk + nblk, ... of p's documents.  RES: the resident
 // schedule only (u and w neither loaded nor stored, every iteration and the
 // final pass in this launch), so the code for the other schedules and the
-// registers it needs are left out.
-template <int TC, int TR, int LG_CG, int MAXW, bool RES>
+// registers it needs are left out.  HALF (one-wave items, lg_cg <= 4): an
+// item spans 32 lanes and a wave holds two; no sum crosses lane bit 5.
+template <int TC, int TR, int LG_CG, int MAXW, bool RES, bool HALF = false>
 __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk) {
+  static_assert(!HALF || (MAXW == 1 && LG_CG <= 4), "half-wave items are one-wave shapes");
   const bool load_u = !RES && p.load_u, store_u = !RES && p.store_u;
   const bool load_w = !RES && p.load_w, store_w = !RES && p.store_w;
   constexpr bool MW = MAXW > 1;                   // an item spans several waves of one block
   constexpr int CG = 1 << LG_CG;
-  constexpr int RSW = 64 >> LG_CG;                // row lanes per wave
+  constexpr int IL = HALF ? 32 : 64;              // lanes per item (within a wave)
+  constexpr int RSW = IL >> LG_CG;                // row lanes per wave and item
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = MW ? (int)(blockDim.x >> 6) : 1;
-  const int cg = lane & (CG - 1);
-  const int rs = (MW ? wave * RSW : 0) + (lane >> LG_CG);
+  const int il = lane & (IL - 1);                 // lane within the item
+  const int cg = il & (CG - 1);
+  const int rs = (MW ? wave * RSW : 0) + (il >> LG_CG);
   const int RS = nwaves * RSW;
-  const int items = MW ? 1 : (int)(blockDim.x >> 6);
-  const int slot = MW ? 0 : wave;
+  const int items = MW ? 1 : (int)(blockDim.x >> 6) * (64 / IL);
+  const int slot = MW ? 0 : wave * (64 / IL) + (HALF ? lane >> 5 : 0);
   constexpr int cw_stride = CG * TC;              // LDS floats per wave and buffer
   const int S = p.S;
   const int vr = *p.vr;
@@ -389,7 +393,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     // Column sums that cross the permlane bits (lane bits 4 and 5) divide in
     // packed form when the row lanes reach them (one-wave items, lg_cg <= 5).
     constexpr bool COLP = !MW && LG_CG <= 5;
-    constexpr int MC = LG_CG <= 4 ? 3 : 2;
+    constexpr int MC = HALF ? 1 : LG_CG <= 4 ? 3 : 2;  // half-wave items: bit 4 only
     float rpk[HighPack<MC, TC>::P];
     if constexpr (COLP) pack_high<MC, TC>(rv, rpk, lane);
     // Row sums over 2, 4, 16, 32 or 64 column lanes divide packed within
@@ -422,6 +426,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
 
     // ---- Sinkhorn-Knopp iterations
     int ran = p.iters;
+    bool done = !active;  // half-wave items under a tolerance: this item has stopped
     for (int it = 0; it < p.iters; ++it) {
       if (!load_w) {
         float s[TR];
@@ -541,12 +546,28 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         // the item holds the same u, so the decision is uniform over the
         // item's waves.
         float dm = 0.f;
+        float uprev[TC];
 #pragma unroll
         for (int e = 0; e < TC; ++e) {
           if (u[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un[e]) * __builtin_amdgcn_rcpf(u[e]));
+          uprev[e] = u[e];
           u[e] = un[e];
         }
         dm = max_low<LG_CG>(dm);
+        if constexpr (HALF) {
+          // two items per wave: an item that has stopped keeps the u of the
+          // iteration it stopped after (restored here), and the wave leaves
+          // the loop once both have stopped
+          if (done) {
+#pragma unroll
+            for (int e = 0; e < TC; ++e) u[e] = uprev[e];
+          } else if (!(dm > p.tol)) {
+            ran = it + 1;
+            done = true;
+          }
+          if (__ballot(!done) == 0) break;
+          continue;
+        }
         // uniform over the wave (one item per wave, or the same value in every
         // wave of a multi-wave item): a scalar branch, so the loop stays free
         // of divergent-exit bookkeeping
@@ -592,7 +613,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       float part[1] = {0.f};
 #pragma unroll
       for (int t = 0; t < TR; ++t) part[0] = fmaf(wf[t], sb[t], part[0]);
-      sum_low<6>(part);
+      sum_low<HALF ? 5 : 6>(part);
       float tot = part[0];
       if constexpr (MW) {
         __syncthreads();  // the last iteration's totals may still be read
@@ -604,7 +625,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         __syncthreads();
       }
       tot *= kNegLn2 * p.inv_lam;
-      if (lane == 0 && (MW ? wave == 0 : true) && active) {
+      if (il == 0 && (MW ? wave == 0 : true) && active) {
         p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
         if (p.iters_out) p.iters_out[k] = ran;
       }
@@ -618,10 +639,11 @@ __global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
   sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x);
 }
 
-// One-wave items, four per block, for several length buckets of one query in
-// a single launch.  Group g holds blocks [end[g-1], end[g]) and documents
-// drec[off[g]] ... drec[off[g] + ndocs[g] - 1]; its rows per lane are TRMAX
-// (body 0), TRMAX/2 (body 1) or TRMAX/4 (body 2), enough for its bucket.
+// One-wave items, four per block (eight as half-wave items), for several
+// length buckets of one query in a single launch.  Group g holds blocks
+// [end[g-1], end[g]) and documents drec[off[g]] ... drec[off[g] + ndocs[g] - 1];
+// body[g] & 3 = 0, 1, 2 gives its rows per lane TRMAX, TRMAX/2 or TRMAX/4, and
+// body[g] & 4 makes its items half-wave (two per wave, 32 lanes each).
 // Groups come longest documents first, so the longest items start first and
 // the short ones fill in behind them.  The other fields of p are shared.
 template <int TC, int TRMAX, int LG_CG, bool RES>
@@ -646,10 +668,26 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
   SinkParams p = m.p;
   p.drec += off;
   p.ndocs = nd;
-  if (body == 0) {
+  const bool half = (body & 4) != 0;
+  const int shift = body & 3;
+  if constexpr (LG_CG <= 4) {
+    if (half) {
+      if (shift == 0) {
+        sink_body<TC, TRMAX, LG_CG, 1, RES, true>(p, b - b0, b1 - b0);
+      } else if constexpr (TRMAX >= 2) {
+        if (shift == 1) {
+          sink_body<TC, TRMAX / 2, LG_CG, 1, RES, true>(p, b - b0, b1 - b0);
+        } else if constexpr (TRMAX >= 4) {
+          sink_body<TC, TRMAX / 4, LG_CG, 1, RES, true>(p, b - b0, b1 - b0);
+        }
+      }
+      return;
+    }
+  }
+  if (shift == 0) {
     sink_body<TC, TRMAX, LG_CG, 1, RES>(p, b - b0, b1 - b0);
   } else if constexpr (TRMAX >= 2) {
-    if (body == 1) {
+    if (shift == 1) {
       sink_body<TC, TRMAX / 2, LG_CG, 1, RES>(p, b - b0, b1 - b0);
     } else if constexpr (TRMAX >= 4) {
       sink_body<TC, TRMAX / 4, LG_CG, 1, RES>(p, b - b0, b1 - b0);

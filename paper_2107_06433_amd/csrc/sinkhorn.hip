@@ -304,17 +304,21 @@ int tr_needed(int lg_cg, int cap) {
   return tr;
 }
 
-double merged_cost(const Shape& variant, const int* tr, const int* nd, int n) {
+// ipw: items per wave (2 for half-wave items, whose column sums span one
+// lane bit fewer).
+double merged_cost(const Shape& variant, const int* tr, const int* ipw, const int* nd, int n) {
   const SinkEntry& e = variant.e;
   const int regs = (variant.regs + 7) & ~7;
   int occ = 512 / regs;
   occ = occ > 8 ? 8 : occ;
   double issue = 0.0, imax = 0.0, waves = 0.0;
   for (int i = 0; i < n; ++i) {
-    const double I = 2.0 * tr[i] * e.tc + tr[i] * e.lg_cg + e.tc * (6 - e.lg_cg) + 2.0 * tr[i] + 2.0 * e.tc;
-    issue += (double)nd[i] * I * 4.0 / 1024.0;
+    const int rbits = (ipw[i] == 2 ? 5 : 6) - e.lg_cg;
+    const double I = 2.0 * tr[i] * e.tc + tr[i] * e.lg_cg + e.tc * rbits + 2.0 * tr[i] + 2.0 * e.tc;
+    const double w = std::ceil((double)nd[i] / ipw[i]);
+    issue += w * I * 4.0 / 1024.0;
     imax = I > imax ? I : imax;
-    waves += nd[i];
+    waves += w;
   }
   const double lat = std::ceil(waves / (1024.0 * occ)) * imax * 8.0;
   return issue > lat ? issue : lat;
@@ -327,7 +331,9 @@ double merged_cost(const Shape& variant, const int* tr, const int* nd, int n) {
 // cover S with the fewest padded columns: the buckets needing at most TRMAX
 // rows per lane join (at least one needing exactly TRMAX), each with the
 // smallest of TRMAX, TRMAX/2, TRMAX/4 that holds it; the others keep launches
-// of their own.  The candidate holding the most buckets wins, the lowest
+// of their own.  A bucket that fits in half a wave at no more than TRMAX rows
+// per lane runs as half-wave items (lg_cg <= 4): two documents per wave and
+// one lane bit fewer in every column sum, which costs less per document.  The candidate holding the most buckets wins, the lowest
 // modelled time (the separate launches included) among equals.  Measured on
 // single queries, one launch over every bucket beat splitting them even where
 // the model preferred a split: the short items fill in behind the long ones.
@@ -342,7 +348,7 @@ bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out)
     if (e.tc * CG < S || (e.tc - 1) * CG >= S) continue;
     MergePlan p{};
     p.tc = e.tc; p.trmax = e.tr; p.lg_cg = e.lg_cg;
-    int trs[kMergeMax], nds[kMergeMax];
+    int trs[kMergeMax], nds[kMergeMax], ipws[kMergeMax];
     bool exact = false;
     double rest = 0.0;
     for (int i = 0; i < nb; ++i) {
@@ -363,16 +369,19 @@ bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out)
         continue;
       }
       exact = exact || t == e.tr;
-      int body = 0;
-      while (body < 2 && (e.tr >> (body + 1)) >= t) ++body;
+      const bool half = e.lg_cg <= 4 && 2 * t <= e.tr;  // half a wave needs twice the rows per lane
+      const int th = half ? 2 * t : t;
+      int shift = 0;
+      while (shift < 2 && (e.tr >> (shift + 1)) >= th) ++shift;
       p.member[p.n] = i;
-      p.body[p.n] = body;
-      trs[p.n] = e.tr >> body;
+      p.body[p.n] = shift | (half ? 4 : 0);
+      trs[p.n] = e.tr >> shift;
+      ipws[p.n] = half ? 2 : 1;
       nds[p.n] = ndocs[i];
       ++p.n;
     }
     if (p.n == 0 || !exact) continue;
-    const double c = merged_cost(sh, trs, nds, p.n) + rest;
+    const double c = merged_cost(sh, trs, ipws, nds, p.n) + rest;
     if (!found || p.n > out->n || (p.n == out->n && c < best)) {
       best = c;
       *out = p;
@@ -400,7 +409,8 @@ hipError_t launch_sink_merged(const SinkParams& p, const MergePlan& plan, const 
   m.ngroups = plan.n;
   int grid = 0;
   for (int g = 0; g < plan.n; ++g) {
-    grid += (ndocs[g] + 3) / 4;
+    const int per_block = (plan.body[g] & 4) ? 8 : 4;  // items per block of four waves
+    grid += (ndocs[g] + per_block - 1) / per_block;
     m.end[g] = grid;
     m.off[g] = off[g];
     m.ndocs[g] = ndocs[g];

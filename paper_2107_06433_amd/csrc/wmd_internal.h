@@ -116,7 +116,7 @@ struct SinkMerge {
   int end[kMergeMax];     // one past the group's last block
   int off[kMergeMax];     // the group's first document record
   int ndocs[kMergeMax];
-  int body[kMergeMax];    // rows per lane TRMAX >> body
+  int body[kMergeMax];    // rows per lane TRMAX >> (body & 3); body & 4: half-wave items
 };
 
 // Register-resident shape: tc x tr cells per lane, 2^lg_cg column lanes, an item
@@ -158,7 +158,8 @@ int sink_block(const SinkConfig& cfg);
 
 // One launch over several length buckets of one query (one-wave items).
 // member[g] indexes the caller's bucket list, longest documents first; group g
-// runs with trmax >> body[g] rows per lane.
+// runs with trmax >> (body[g] & 3) rows per lane, as half-wave items (two per
+// wave) when body[g] & 4.
 struct MergePlan {
   int tc = 0, trmax = 0, lg_cg = 0;
   int n = 0;
