@@ -368,9 +368,9 @@ bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out)
         rest += alone[(size_t)i];
         continue;
       }
-      exact = exact || t == e.tr;
       const bool half = e.lg_cg <= 4 && 2 * t <= e.tr;  // half a wave needs twice the rows per lane
       const int th = half ? 2 * t : t;
+      exact = exact || th == e.tr;
       int shift = 0;
       while (shift < 2 && (e.tr >> (shift + 1)) >= th) ++shift;
       p.member[p.n] = i;
