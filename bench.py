@@ -205,8 +205,8 @@ def serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
-              "Documents shard across GPUs with no per-iteration exchange; see DESIGN.md.", file=sys.stderr)
+        print(f"bench.py measures one GPU: no multi-GPU path is implemented (asked for --gpus {args.gpus}). "
+              "Documents would shard across GPUs with no per-iteration exchange.", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -268,7 +268,7 @@ class Corpus:
                 self.set_sink_shape(S, cap, shape)
                 n += 1
             except WMDError:
-                pass  # a shape this build cannot run for that key: keep the model's choice
+                pass  # a shape the library cannot run for that key: keep the model's choice
         self.pinned = n
         return n
 
