@@ -25,6 +25,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int BM, int BN, int WM, bool BF16, int BK_>
 struct Tile {
@@ -238,8 +239,16 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
 // MFMA operand registers -- for every 16 (f32) or 32 (bf16) k values, the four
 // lane quads of a row read one contiguous 64-byte piece.  All loads of a row
 // (CH steps) are issued at once, so one memory latency covers the whole row.
-template <int NT, bool BF16, int CH>
+//
+// NT tiles of 16 query columns use 16x16 MFMAs.  F32 inputs may add N4 groups
+// of 4 columns on v_mfma_f32_4x4x1_16b_f32, whose 16 blocks here are 4 row
+// quads x 4 k slices of the same operand registers (lane l: row l & 15, k
+// slice l >> 4, as for the 16x16 shape), so a 4-column group costs a quarter
+// of a 16-column tile.  The k slices are summed once at the end.
+template <int NT, int N4, bool BF16, int CH>
 __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
+  static_assert(!BF16 || N4 == 0, "4-column groups are an f32 path");
+  static_assert(NT + N4 > 0, "no columns");
   constexpr int ESZ = BF16 ? 2 : 4;
   constexpr int KS = BF16 ? 32 : 16;        // k values per 16-byte-per-lane load step
   // CH = dp / KS load steps: the whole row, a compile-time count, and every
@@ -248,7 +257,8 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   constexpr int ROWB = CH * KS * ESZ;       // bytes per embedding row (64 per step)
   constexpr int LDQ = ROWB + 16;            // LDS row pitch in bytes (one 16-byte pad)
   constexpr int VPR = ROWB / 16;            // 16-byte pieces per row
-  constexpr int QTOT = NT * 16 * VPR;       // pieces of the Q tile
+  constexpr int QROWS = NT * 16 + N4 * 4;   // Q rows staged in LDS
+  constexpr int QTOT = QROWS * VPR;         // pieces of the Q tile
   constexpr int QPT = (QTOT + 255) / 256;   // per thread
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -257,22 +267,23 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   const bool row_ok = myrow < p.U;
   const unsigned char* Ag = (BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32) +
                             (size_t)(row_ok ? myrow : 0) * ROWB + 16 * (lane >> 4);
-  f32x4 acc[NT];
+  f32x4 acc[NT > 0 ? NT : 1], acc4[N4 > 0 ? N4 : 1];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // Q: NT*16 rows go to LDS through registers.  Its loads are issued first
+#pragma unroll
+  for (int u = 0; u < N4; ++u) acc4[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // Q: QROWS rows go to LDS through registers.  Its loads are issued first
   // and its LDS stores come after the vocabulary row's loads: loads retire in
   // order, so the stores wait for the Q pieces alone while the row is already
-  // in flight.  Rows past C repeat Q's first piece: each output column depends
-  // on its own Q row only, and the epilogue never stores those columns.
+  // in flight.  Rows past C repeat row C - 1: each output column depends on its
+  // own Q row only, and the epilogue never stores those columns.
   const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
   uint4 qv[QPT];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
-    const int i = j * 256 + tid;
+    const int i = QTOT % 256 == 0 ? j * 256 + tid : min(j * 256 + tid, QTOT - 1);
     const int row = i / VPR;
-    const bool ok = (QTOT % 256 == 0 || i < QTOT) && row < p.C;
-    qv[j] = *(const uint4*)(Qg + (ok ? (size_t)row * ROWB + 16 * (i - row * VPR) : 0));
+    qv[j] = *(const uint4*)(Qg + (size_t)min(row, (int)p.C - 1) * ROWB + 16 * (i - row * VPR));
   }
   uint4 buf[CH];
 #pragma unroll
@@ -288,9 +299,10 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     en_r[i] = p.en[mc];
     used_r[i] = p.used[mc];
   }
-  int q_c[NT];
-  float qn_c[NT];
-  int2 ci_c[NT];
+  constexpr int NTA = NT > 0 ? NT : 1;
+  int q_c[NTA];
+  float qn_c[NTA];
+  int2 ci_c[NTA];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int64_t n = t * 16 + (lane & 15);
@@ -299,11 +311,47 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     qn_c[t] = p.qn[nc];
     ci_c[t] = p.cinfo[nc];
   }
+  // 4-column groups: lane l ends with row 4 ((l >> 2) & 3) + (l >> 4) of the
+  // wave's 16 and column 4 u + (l & 3) of group u
+  const int64_t m4 = m0 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+  float en_4 = 0.f;
+  int used_4 = 0;
+  int q_4[N4 > 0 ? N4 : 1];
+  float qn_4[N4 > 0 ? N4 : 1];
+  int2 ci_4[N4 > 0 ? N4 : 1];
+  if constexpr (N4 > 0) {
+    const int64_t mc = m4 < p.U ? m4 : p.U - 1;
+    en_4 = p.en[mc];
+    used_4 = p.used[mc];
+  }
+#pragma unroll
+  for (int u = 0; u < N4; ++u) {
+    const int64_t n = NT * 16 + 4 * u + (lane & 3);
+    const int64_t nc = n < p.C ? n : p.C - 1;
+    q_4[u] = p.qid[nc];
+    qn_4[u] = p.qn[nc];
+    ci_4[u] = p.cinfo[nc];
+  }
+  // An empty asm that takes and returns the Q pieces keeps their LDS stores
+  // (and the waits for them) below every load above, which the scheduler
+  // would otherwise interleave with the row's loads.  It keeps the pieces live
+  // across the row's loads, so only where the registers allow three waves
+  // per SIMD.
+  if constexpr (4 * (CH + QPT) <= 108) {
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+      u32x4 t = __builtin_bit_cast(u32x4, qv[j]);
+      asm volatile("" : "+v"(t));
+      qv[j] = __builtin_bit_cast(uint4, t);
+    }
+  }
+  // threads past the tile repeat the last piece (same value, same address):
+  // every store is unconditional, so none waits for more than its own load
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
-    const int i = j * 256 + tid;
+    const int i = QTOT % 256 == 0 ? j * 256 + tid : min(j * 256 + tid, QTOT - 1);
     const int row = i / VPR;
-    if (QTOT % 256 == 0 || i < QTOT) *(uint4*)(smem + row * LDQ + 16 * (i - row * VPR)) = qv[j];
+    *(uint4*)(smem + row * LDQ + 16 * (i - row * VPR)) = qv[j];
   }
   __syncthreads();
   {
@@ -323,8 +371,25 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
           for (int j = 0; j < 4; ++j) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[t], 0, 0, 0);
         }
       }
+      if constexpr (!BF16) {
+#pragma unroll
+        for (int u = 0; u < N4; ++u) {
+          const uint4 q = *(const uint4*)(smem + (NT * 16 + 4 * u + (lane & 3)) * LDQ + kb);
+          const f32x4 a = __builtin_bit_cast(f32x4, buf[i]);
+          const f32x4 b = __builtin_bit_cast(f32x4, q);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc4[u] = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b[j], acc4[u], 0, 0, 0);
+        }
+      }
     }
   }
+  // 4-column groups: register i of lane l holds row 4 ((l >> 2) & 3) + i,
+  // column l & 3, summed over k slice l >> 4; a reduce-scatter over the k
+  // slices leaves lane l the total of register l >> 4
+  float k4[N4 > 0 ? N4 : 1];
+#pragma unroll
+  for (int u = 0; u < N4; ++u)
+    k4[u] = sum_scatter32(sum_scatter16(acc4[u][0], acc4[u][1]), sum_scatter16(acc4[u][2], acc4[u][3]));
   // epilogue: register i of lane l holds row 4*(l/16)+i, column l%16 of each
   // tile.  All K values first, then the stores (a store counts against the
   // same memory counter as a load; nothing waits on them).
@@ -338,6 +403,18 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
       acc[t][i] = q_c[t] >= 0 ? expf(-p.lam * dist) : 1.f;
     }
 #pragma unroll
+  for (int u = 0; u < N4; ++u) {
+    const float m2 = en_4 + qn_4[u] - 2.f * k4[u];
+    const float dist = used_4 == q_4[u] ? 0.f : sqrtf(fmaxf(m2, 0.f));
+    k4[u] = q_4[u] >= 0 ? expf(-p.lam * dist) : 1.f;
+  }
+#pragma unroll
+  for (int u = 0; u < N4; ++u) {
+    const int64_t n = NT * 16 + 4 * u + (lane & 3);
+    if (n < p.C && m4 < p.U)
+      p.kt[(size_t)ci_4[u].x * (size_t)p.U + (n - ci_4[u].x) + (size_t)m4 * ci_4[u].y] = k4[u];
+  }
+#pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int64_t n = t * 16 + (lane & 15);
     float* kt = p.kt + (size_t)ci_c[t].x * (size_t)p.U + (n - ci_c[t].x);
@@ -349,40 +426,58 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   }
 }
 
-template <int NT, bool BF16, int CH>
+size_t skinny_lds(int nt, int n4, int dp, bool bf16) {
+  return (size_t)(nt * 16 + n4 * 4) * (size_t)(dp * (bf16 ? 2 : 4) + 16);
+}
+
+template <int NT, int N4, bool BF16, int CH>
 hipError_t run_skinny_ch(const CdistParams& p, hipStream_t s) {
-  const size_t lds = (size_t)NT * 16 * (p.dp * (BF16 ? 2 : 4) + 16);
   const unsigned grid = (unsigned)((p.U + 63) / 64);
-  cdist_skinny_kernel<NT, BF16, CH><<<grid, 256, lds, s>>>(p);
+  cdist_skinny_kernel<NT, N4, BF16, CH><<<grid, 256, skinny_lds(NT, N4, p.dp, BF16), s>>>(p);
   return hipGetLastError();
 }
 
 // the skinny kernel instantiated for this row length (dp / (16 / elem bytes)
 // load steps), or hipErrorInvalidValue when there is none
-template <int NT, bool BF16>
+template <int NT, int N4, bool BF16>
 hipError_t run_skinny(const CdistParams& p, hipStream_t s) {
   const int steps = p.dp / (BF16 ? 32 : 16);
   switch (steps) {
-    case 4: return run_skinny_ch<NT, BF16, 4>(p, s);
-    case 8: return run_skinny_ch<NT, BF16, 8>(p, s);
-    case 12: return run_skinny_ch<NT, BF16, 12>(p, s);
-    case 16: return run_skinny_ch<NT, BF16, 16>(p, s);
-    case 20: return run_skinny_ch<NT, BF16, 20>(p, s);
-    case 24: return run_skinny_ch<NT, BF16, 24>(p, s);
+    case 4: return run_skinny_ch<NT, N4, BF16, 4>(p, s);
+    case 8: return run_skinny_ch<NT, N4, BF16, 8>(p, s);
+    case 12: return run_skinny_ch<NT, N4, BF16, 12>(p, s);
+    case 16: return run_skinny_ch<NT, N4, BF16, 16>(p, s);
+    case 20: return run_skinny_ch<NT, N4, BF16, 20>(p, s);
+    case 24: return run_skinny_ch<NT, N4, BF16, 24>(p, s);
     default: break;
   }
   if constexpr (BF16) {
     switch (steps) {
-      case 2: return run_skinny_ch<NT, BF16, 2>(p, s);
-      case 6: return run_skinny_ch<NT, BF16, 6>(p, s);
-      case 10: return run_skinny_ch<NT, BF16, 10>(p, s);
-      case 14: return run_skinny_ch<NT, BF16, 14>(p, s);
-      case 18: return run_skinny_ch<NT, BF16, 18>(p, s);
-      case 22: return run_skinny_ch<NT, BF16, 22>(p, s);
+      case 2: return run_skinny_ch<NT, N4, BF16, 2>(p, s);
+      case 6: return run_skinny_ch<NT, N4, BF16, 6>(p, s);
+      case 10: return run_skinny_ch<NT, N4, BF16, 10>(p, s);
+      case 14: return run_skinny_ch<NT, N4, BF16, 14>(p, s);
+      case 18: return run_skinny_ch<NT, N4, BF16, 18>(p, s);
+      case 22: return run_skinny_ch<NT, N4, BF16, 22>(p, s);
       default: break;
     }
   }
   return hipErrorInvalidValue;
+}
+
+// F32, C <= 32: the fewest MFMA cycles per 16 rows -- 16-column tiles (32
+// cycles per k step of 4) and 4-column groups (8 cycles) -- covering C
+hipError_t run_skinny_f32(const CdistParams& p, hipStream_t s, const char** name) {
+  switch ((p.C + 3) / 4) {
+    case 1: *name = "cdist_skinny_kernel<0,1,0>"; return run_skinny<0, 1, false>(p, s);
+    case 2: *name = "cdist_skinny_kernel<0,2,0>"; return run_skinny<0, 2, false>(p, s);
+    case 3: *name = "cdist_skinny_kernel<0,3,0>"; return run_skinny<0, 3, false>(p, s);
+    case 4: *name = "cdist_skinny_kernel<1,0,0>"; return run_skinny<1, 0, false>(p, s);
+    case 5: *name = "cdist_skinny_kernel<1,1,0>"; return run_skinny<1, 1, false>(p, s);
+    case 6: *name = "cdist_skinny_kernel<1,2,0>"; return run_skinny<1, 2, false>(p, s);
+    case 7: *name = "cdist_skinny_kernel<1,3,0>"; return run_skinny<1, 3, false>(p, s);
+    default: *name = "cdist_skinny_kernel<2,0,0>"; return run_skinny<2, 0, false>(p, s);
+  }
 }
 
 bool skinny_steps_ok(int dp, bool bf16) {
@@ -394,15 +489,16 @@ bool skinny_steps_ok(int dp, bool bf16) {
 
 hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name) {
   if (p.U <= 0 || p.C <= 0) return hipSuccess;
-  const size_t skinny_lds = (size_t)32 * (p.dp * (bf16 ? 2 : 4) + 16);
-  const bool skinny = skinny_steps_ok(p.dp, bf16);
-  if (skinny && p.C <= 16 && skinny_lds / 2 <= 65536) {
-    *name = bf16 ? "cdist_skinny_kernel<1,1>" : "cdist_skinny_kernel<1,0>";
-    return bf16 ? run_skinny<1, true>(p, s) : run_skinny<1, false>(p, s);
+  // the skinny kernel whenever its Q tile (at most 32 rows) fits in 64 KiB of LDS
+  const bool skinny = skinny_steps_ok(p.dp, bf16) && skinny_lds(2, 0, p.dp, bf16) <= 65536;
+  if (skinny && !bf16 && p.C <= 32) return run_skinny_f32(p, s, name);
+  if (skinny && p.C <= 16) {
+    *name = "cdist_skinny_kernel<1,0,1>";
+    return run_skinny<1, 0, true>(p, s);
   }
-  if (skinny && p.C <= 32 && skinny_lds <= 65536) {
-    *name = bf16 ? "cdist_skinny_kernel<2,1>" : "cdist_skinny_kernel<2,0>";
-    return bf16 ? run_skinny<2, true>(p, s) : run_skinny<2, false>(p, s);
+  if (skinny && p.C <= 32) {
+    *name = "cdist_skinny_kernel<2,0,1>";
+    return run_skinny<2, 0, true>(p, s);
   }
   if (p.C <= 32) {
     *name = bf16 ? "cdist_kernel<64,32,4,1,64>" : "cdist_kernel<64,32,4,0,32>";

@@ -409,8 +409,10 @@ def test_embedding_widths_off_the_vector_path(W, d):
         assert_close(got16[b], ref, TOL16, f"d={d} bf16 query {b}")
 
 
-@pytest.mark.parametrize("vr", [1, 3, 4, 5, 63, 64, 65, 500, 2048])
+@pytest.mark.parametrize("vr", [1, 3, 4, 5, 9, 13, 21, 27, 30, 63, 64, 65, 500, 2048])
 def test_query_widths(W, vr):
+    """Every skinny cost-matrix column split (4-column groups, 16-column
+    tiles and both) up to 32 padded columns, then the tiled kernel."""
     rng = np.random.default_rng(43 + vr)
     c = handmade_corpus(rng, 4000, 24, rng.integers(1, 60, size=50))
     ids = rng.choice(4000, size=vr, replace=False).astype(np.int32)
