@@ -17,6 +17,7 @@
 // as A and B use the same one, so each lane feeds a run of consecutive k
 // values read with one 16-byte LDS load.
 #include "lanes.h"
+#include "query_rows.h"
 #include "wmd_internal.h"
 
 namespace wmd {
@@ -245,7 +246,13 @@ hipError_t run(const CdistParams& p, hipStream_t s) {
 // quads x 4 k slices of the same operand registers (lane l: row l & 15, k
 // slice l >> 4, as for the 16x16 shape), so a 4-column group costs a quarter
 // of a 16-column tile.  The k slices are summed once at the end.
-template <int NT, int N4, bool BF16, int CH>
+//
+// SEL: the query (one, of at most 64 entries) is selected here instead of by
+// the selection kernel: while the row's loads are in flight, wave 0 selects
+// it, then 8 lanes per slot read its embedding rows straight into the Q tile
+// with the selection kernel's own row reader (same values, same norms), and
+// block 0 writes the selection's outputs for the kernels that follow.
+template <int NT, int N4, bool BF16, int CH, bool SEL>
 __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   static_assert(!BF16 || N4 == 0, "4-column groups are an f32 path");
   static_assert(NT + N4 > 0, "no columns");
@@ -280,31 +287,39 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   const unsigned char* Qg = BF16 ? (const unsigned char*)p.q16 : (const unsigned char*)p.q32;
   uint4 qv[QPT];
 #pragma unroll
-  for (int j = 0; j < QPT; ++j) {
+  for (int j = 0; j < (SEL ? 0 : QPT); ++j) {
     const int i = QTOT % 256 == 0 ? j * 256 + tid : min(j * 256 + tid, QTOT - 1);
     const int row = i / VPR;
     qv[j] = *(const uint4*)(Qg + (size_t)min(row, (int)p.C - 1) * ROWB + 16 * (i - row * VPR));
   }
   uint4 buf[CH];
-#pragma unroll
-  for (int i = 0; i < CH; ++i) buf[i] = *(const uint4*)(Ag + (size_t)i * 64);
-  // the epilogue's per-row and per-column data, fetched early for the same
-  // reason (indices clamped)
   float en_r[4];
   int used_r[4];
+  auto load_rows = [&]() {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t m = m0 + 4 * (lane >> 4) + i;
-    const int64_t mc = m < p.U ? m : p.U - 1;
-    en_r[i] = p.en[mc];
-    used_r[i] = p.used[mc];
-  }
+    for (int i = 0; i < CH; ++i) buf[i] = *(const uint4*)(Ag + (size_t)i * 64);
+    // the epilogue's per-row and per-column data, fetched early for the same
+    // reason (indices clamped)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t m = m0 + 4 * (lane >> 4) + i;
+      const int64_t mc = m < p.U ? m : p.U - 1;
+      en_r[i] = p.en[mc];
+      used_r[i] = p.used[mc];
+    }
+  };
+  // SEL, f32: wave 0 selects first and reads its rows afterwards (loads
+  // return in order: the selection's would otherwise wait behind the row's).
+  // With bf16 rows (half the bytes) starting wave 0's rows late cost more
+  // than the wait (measured), so there every wave reads its rows first.
+  constexpr bool SEL_FIRST = SEL && !BF16;
+  if (!SEL_FIRST || wave != 0) load_rows();
   constexpr int NTA = NT > 0 ? NT : 1;
   int q_c[NTA];
   float qn_c[NTA];
   int2 ci_c[NTA];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
+  for (int t = 0; t < (SEL ? 0 : NT); ++t) {
     const int64_t n = t * 16 + (lane & 15);
     const int64_t nc = n < p.C ? n : p.C - 1;
     q_c[t] = p.qid[nc];
@@ -325,7 +340,7 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     used_4 = p.used[mc];
   }
 #pragma unroll
-  for (int u = 0; u < N4; ++u) {
+  for (int u = 0; u < (SEL ? 0 : N4); ++u) {
     const int64_t n = NT * 16 + 4 * u + (lane & 3);
     const int64_t nc = n < p.C ? n : p.C - 1;
     q_4[u] = p.qid[nc];
@@ -337,7 +352,7 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   // would otherwise interleave with the row's loads.  It keeps the pieces live
   // across the row's loads, so only where the registers allow three waves
   // per SIMD.
-  if constexpr (4 * (CH + QPT) <= 108) {
+  if constexpr (!SEL && 4 * (CH + QPT) <= 108) {
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
       u32x4 t = __builtin_bit_cast(u32x4, qv[j]);
@@ -348,12 +363,125 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   // threads past the tile repeat the last piece (same value, same address):
   // every store is unconditional, so none waits for more than its own load
 #pragma unroll
-  for (int j = 0; j < QPT; ++j) {
+  for (int j = 0; j < (SEL ? 0 : QPT); ++j) {
     const int i = QTOT % 256 == 0 ? j * 256 + tid : min(j * 256 + tid, QTOT - 1);
     const int row = i / VPR;
     *(uint4*)(smem + row * LDQ + 16 * (i - row * VPR)) = qv[j];
   }
-  __syncthreads();
+  if constexpr (SEL) {
+    static_assert(QROWS <= 32, "at most 32 slots");
+    __shared__ int s_id[64], s_slot[64], s_qid[32];
+    __shared__ double s_m[64];
+    __shared__ float s_qn[32];
+    __shared__ int s_err, s_vr;
+    __shared__ double s_tot;
+    const int S = (int)p.C;
+    // Q row g = slot g's embedding row (zeros past the words), 8 lanes per
+    // row, as the selection kernel reads them: the same chunks per lane, the
+    // same norm order
+    constexpr int DPC = CH * KS;                // padded width
+    constexpr int NCH = (DPC + 31) / 32;        // chunks per lane and row
+    const int lane8 = lane & 7;
+    auto row_of = [&](int g) {
+      const int e = g < s_vr ? s_slot[g] : -1;
+      return e >= 0 ? s_id[e] : -1;
+    };
+    auto fetch = [&](int q, float4(&xr)[NCH]) {
+#pragma unroll
+      for (int i = 0; i < NCH; ++i) xr[i] = query_chunk(p.emb, p.d, q, 4 * (lane8 + 8 * i));
+    };
+    auto emit = [&](int g, int q, const float4(&xr)[NCH]) {
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < NCH; ++i) {
+        const int k = 4 * (lane8 + 8 * i);
+        if (k < DPC) {
+          if (g < QROWS) {
+            if constexpr (BF16)
+              *(uint2*)(smem + g * LDQ + 2 * k) = pack_bf16x4(xr[i]);
+            else
+              *(float4*)(smem + g * LDQ + 4 * k) = xr[i];
+          }
+          nrm = add_squares(nrm, xr[i]);
+        }
+      }
+      nrm = sum_row_lanes(nrm);
+      if (g < QROWS && lane8 == 0) {
+        s_qn[g] = (float)nrm;
+        s_qid[g] = q;
+      }
+    };
+    if (wave == 0) {
+      select_small(p.q_ids, p.q_w, p.V, 0, p.sel_n, S, lane, s_id, s_m, s_slot, &s_err, &s_vr, &s_tot);
+      __builtin_amdgcn_wave_barrier();
+      const int vr = s_vr;
+      if (blockIdx.x == 0) {
+        if (lane == 0) {
+          const int err = s_err;
+          p.err[0] = err & 1 ? 1 : err & 2 ? 2 : err & 4 ? 4 : err & 8 ? 3 : 0;
+          p.vr[0] = vr;
+        }
+        if (lane < S) {
+          const int i = lane < vr ? s_slot[lane] : -1;
+          p.qid_out[lane] = i >= 0 ? s_id[i] : -1;
+          p.r[lane] = i >= 0 ? (float)(s_m[i] / s_tot) : 0.f;
+          p.cinfo_out[lane] = make_int2(0, S);
+        }
+      }
+      if constexpr (SEL_FIRST) {
+        // wave 0 alone, 8 rows per pass, every pass's loads in flight at once
+        // when the registers allow; its own rows after that
+        constexpr int PASSES = (QROWS + 7) / 8;
+        constexpr bool BATCH = PASSES * NCH <= 32;
+        float4 x[BATCH ? PASSES : 1][NCH];
+        int qr[PASSES];
+#pragma unroll
+        for (int r = 0; r < PASSES; ++r) qr[r] = row_of(8 * r + (lane >> 3));
+        if constexpr (BATCH) {
+#pragma unroll
+          for (int r = 0; r < PASSES; ++r) fetch(qr[r], x[r]);
+#pragma unroll
+          for (int r = 0; r < PASSES; ++r) emit(8 * r + (lane >> 3), qr[r], x[r]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < PASSES; ++r) {
+            fetch(qr[r], x[0]);
+            emit(8 * r + (lane >> 3), qr[r], x[0]);
+          }
+        }
+        load_rows();
+      }
+    }
+    if constexpr (!SEL_FIRST) {
+      // every wave's rows are in flight already: all 32 groups of 8 lanes
+      // read one Q row each
+      __syncthreads();
+      const int g = tid >> 3;
+      const int q = row_of(g);
+      float4 x[NCH];
+      fetch(q, x);
+      emit(g, q, x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = t * 16 + (lane & 15);
+      const int nc = n < S ? n : S - 1;
+      q_c[t] = s_qid[nc];
+      qn_c[t] = s_qn[nc];
+      ci_c[t] = make_int2(0, S);
+    }
+#pragma unroll
+    for (int u = 0; u < N4; ++u) {
+      const int n = NT * 16 + 4 * u + (lane & 3);
+      const int nc = n < S ? n : S - 1;
+      q_4[u] = s_qid[nc];
+      qn_4[u] = s_qn[nc];
+      ci_4[u] = make_int2(0, S);
+    }
+  } else {
+    __syncthreads();
+  }
   {
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
@@ -433,7 +561,10 @@ size_t skinny_lds(int nt, int n4, int dp, bool bf16) {
 template <int NT, int N4, bool BF16, int CH>
 hipError_t run_skinny_ch(const CdistParams& p, hipStream_t s) {
   const unsigned grid = (unsigned)((p.U + 63) / 64);
-  cdist_skinny_kernel<NT, N4, BF16, CH><<<grid, 256, skinny_lds(NT, N4, p.dp, BF16), s>>>(p);
+  if (p.sel_n > 0)
+    cdist_skinny_kernel<NT, N4, BF16, CH, true><<<grid, 256, skinny_lds(NT, N4, p.dp, BF16), s>>>(p);
+  else
+    cdist_skinny_kernel<NT, N4, BF16, CH, false><<<grid, 256, skinny_lds(NT, N4, p.dp, BF16), s>>>(p);
   return hipGetLastError();
 }
 
@@ -487,10 +618,18 @@ bool skinny_steps_ok(int dp, bool bf16) {
 
 }  // namespace
 
+// the skinny kernel whenever its Q tile (at most 32 rows) fits in 64 KiB of LDS
+static bool skinny_fits(const CdistParams& p, bool bf16) {
+  return skinny_steps_ok(p.dp, bf16) && skinny_lds(2, 0, p.dp, bf16) <= 65536 && p.C <= 32;
+}
+
+bool cdist_fuses_select(const CdistParams& p, bool bf16) { return p.U > 0 && p.C > 0 && skinny_fits(p, bf16); }
+
 hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name) {
   if (p.U <= 0 || p.C <= 0) return hipSuccess;
-  // the skinny kernel whenever its Q tile (at most 32 rows) fits in 64 KiB of LDS
-  const bool skinny = skinny_steps_ok(p.dp, bf16) && skinny_lds(2, 0, p.dp, bf16) <= 65536;
+  if (p.sel_n > 0 && (!cdist_fuses_select(p, bf16) || p.sel_n > 64 || p.C != ((p.sel_n + 3) & ~3)))
+    return hipErrorInvalidValue;
+  const bool skinny = skinny_fits(p, bf16);
   if (skinny && !bf16 && p.C <= 32) return run_skinny_f32(p, s, name);
   if (skinny && p.C <= 16) {
     *name = "cdist_skinny_kernel<1,0,1>";

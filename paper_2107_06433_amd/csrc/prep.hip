@@ -90,73 +90,6 @@ __global__ void prep_emb_kernel(const float* emb, int d, int dp, const int* used
   }
 }
 
-// Sum of a double over the 64 lanes, every lane receiving the same total:
-// DPP moves of both halves within 16-lane rows (lower bits first, so the
-// mirror patterns pair lanes holding equal partial sums), then the permlane
-// swaps across rows.
-__device__ __forceinline__ double sum_wave_f64(double x) {
-  x += dpp_f64<kDppXor1>(x);
-  x += dpp_f64<kDppXor2>(x);
-  x += dpp_f64<kDppHalfMirror>(x);
-  x += dpp_f64<kDppMirror>(x);
-  auto cross = [&](bool half) {
-    const uint64_t u = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
-    auto pl = half ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
-                   : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    auto ph = half ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
-                   : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    x = __longlong_as_double((long long)(((uint64_t)ph[0] << 32) | pl[0])) +
-        __longlong_as_double((long long)(((uint64_t)ph[1] << 32) | pl[1]));
-  };
-  cross(false);
-  cross(true);
-  return x;
-}
-
-// Selection for a query of at most 64 entries, by one wave with one entry per
-// lane: repeats are merged by broadcasting each entry in turn (readlane), so
-// the merge needs no LDS round trips and no barriers.  Same results as the
-// general path: each first occurrence sums its repeats in entry order, slots
-// follow entry order.  Writes s_id/s_m for the entries, s_slot for the S
-// slots and the query's error code, word count and total weight.
-__device__ __forceinline__ void select_small(const SelectParams& p, int64_t beg, int n, int S, int lane,
-                                             int* s_id, double* s_m, int* s_slot, int* s_err, int* s_vr,
-                                             double* s_tot) {
-  const bool in = lane < n;
-  const int id = in ? p.q_ids[beg + lane] : -1;
-  const float x = in ? p.q_w[beg + lane] : 0.f;
-  const bool bad_id = in && (id < 0 || id >= p.V);
-  const bool bad_w = in && (!(x >= 0.f) || isinf(x));
-  const bool f1 = __ballot(bad_id) != 0, f2 = __ballot(bad_w) != 0;
-  bool first = true;
-  double m = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const int idj = __builtin_amdgcn_readlane(id, j);
-    const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-    const bool eq = idj == id;
-    first = first && !(eq && j < lane);
-    m += (eq && j >= lane) ? (double)wj : 0.0;  // adding +0.0 leaves m unchanged
-  }
-  const bool sel = in && first && m > 0.0;
-  const unsigned long long mask = __ballot(sel);
-  const int c = __popcll(mask);
-  if (sel) s_slot[__popcll(mask & ((1ull << lane) - 1))] = lane;
-  if (lane >= c && lane < S) s_slot[lane] = -1;
-  if (in) {
-    s_id[lane] = id;
-    s_m[lane] = first ? m : 0.0;
-  }
-  const double tot = sum_wave_f64(sel ? m : 0.0);
-  if (lane == 0) {
-    int e = (f1 ? 1 : 0) | (f2 ? 2 : 0);
-    if (e == 0 && c == 0) e = 8;
-    *s_err = e;
-    *s_vr = e ? 0 : c;
-    *s_tot = tot;
-  }
-}
-
 // Algorithm 1, first step, for one query per block: validate the entries,
 // sum repeated ids, drop zero weights, normalise r in double, and lay out the
 // query's S slots (S = entries rounded up to 4) of the GEMM's column space:
@@ -186,7 +119,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
     if (lane == 0) s_col0 = part;
   }
   if (n <= 64) {
-    if (wave == 0) select_small(p, beg, n, S, lane, s_id, s_m, s_slot, &s_err, &s_vr, &s_tot);
+    if (wave == 0) select_small(p.q_ids, p.q_w, p.V, beg, n, S, lane, s_id, s_m, s_slot, &s_err, &s_vr, &s_tot);
     __syncthreads();
   } else {
   // entries into LDS, with their error flags ORed per wave

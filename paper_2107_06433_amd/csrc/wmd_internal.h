@@ -85,6 +85,15 @@ struct CdistParams {
   const float* q32; const uint16_t* q16; const float* qn; const int* qid; const int2* cinfo;
   int64_t C; int dp; float lam;
   float* kt;
+  // Fused selection (sel_n > 0): one query of sel_n <= 64 entries and C = its
+  // padded width.  Every block selects it and reads the embedding rows of its
+  // words itself; block 0 also writes err, vr, r, qid and cinfo (the _out
+  // pointers to the same buffers as qid and cinfo), the outputs
+  // of the selection kernel that the later kernels read.  q32, q16 and qn are
+  // then neither read nor written.
+  int sel_n;
+  const int32_t* q_ids; const float* q_w; int64_t V; int d; const float* emb;
+  int* err; int* vr; float* r; int* qid_out; int2* cinfo_out;
 };
 
 // One fused SDDMM-SpMM launch over the documents of one length bucket for one
@@ -143,6 +152,8 @@ hipError_t launch_prep_emb(const float* emb, int d, int dp, const int* used, int
 hipError_t launch_select(const SelectParams& p, hipStream_t s);
 // `name` receives the kernel and tile shape that was launched.
 hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name);
+// whether launch_cdist can run with the selection fused in (sel_n > 0)
+bool cdist_fuses_select(const CdistParams& p, bool bf16);
 hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s);
 hipError_t launch_nan_docs(const int* docs, int64_t ndocs, float* out, hipStream_t s);
 

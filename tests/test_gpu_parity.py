@@ -222,6 +222,34 @@ def test_batch_invariance(W, batched):
         assert np.array_equal(alone, full[b]), f"query {b} differs alone vs in the batch"
 
 
+@pytest.mark.parametrize("vr", [3, 8, 12, 16, 20, 24, 28, 32])
+def test_narrow_query_alone_and_among_wide_ones(W, vr):
+    """A query of at most 32 padded columns alone runs the skinny cost-matrix
+    kernel; among wide queries its columns go through the tiled kernel.  Both
+    add the k products of a 16-column tile in the same order, so bf16 inputs
+    and f32 widths of whole tiles (16, 32) give identical bits.  The f32
+    4-column groups (widths 17-28 and at most 12) add k in four interleaved
+    partial sums: the same distances to within a few float32 ulp."""
+    rng = np.random.default_rng(700 + vr)
+    c = handmade_corpus(rng, 3000, 300, rng.integers(5, 60, size=300))
+    corpus = corpus_of(W, c)
+    wide = [(rng.choice(3000, 60, replace=False), rng.integers(1, 4, 60)) for _ in range(2)]
+    q = (rng.choice(3000, vr, replace=False), rng.integers(1, 4, vr))
+
+    def batch(qs):
+        return synth.Queries(q_ptr=np.concatenate([[0], np.cumsum([len(a) for a, _ in qs])]),
+                             ids=np.concatenate([a for a, _ in qs]).astype(np.int32),
+                             weights=np.concatenate([x for _, x in qs]).astype(np.float32))
+
+    for cd in ("fp32", "bf16"):
+        alone = run(W, corpus, batch([q]), 10.0, 15, cdist=cd)[0]
+        among = run(W, corpus, batch([wide[0], q, wide[1]]), 10.0, 15, cdist=cd)[1]
+        if cd == "bf16" or (vr + 3) // 4 * 4 in (16, 32):
+            assert np.array_equal(alone, among), f"{cd} v_r={vr}: alone differs from among wide queries"
+        else:
+            assert_close(alone, among, 1e-6, f"{cd} v_r={vr}: alone vs among wide queries")
+
+
 def test_graph_replays_match_eager(W, batched):
     """Captured launches replay bit-identically to eager calls, with eager
     work (a fill of the output, another query on another stream) between the
@@ -301,25 +329,32 @@ def test_empty_zero_weight_and_duplicate_entries(W):
 def test_short_and_long_query_selection_agree(W):
     """Queries of at most 64 entries are selected by one wave, longer ones by
     the block-wide path.  The same words, with repeats and zero weights, padded
-    past 64 entries with more zero weights, give the same distances (to the
-    rounding of a different slot width) and both match the oracle."""
+    with more zero weights to 50 and 70 entries, give the same distances (to
+    the rounding of a different slot width) and match the oracle, first in
+    the call or last."""
     rng = np.random.default_rng(46)
     c = handmade_corpus(rng, 400, 24, rng.integers(1, 40, size=60))
-    base_ids = rng.choice(400, size=30, replace=False)
-    ids_a = np.concatenate([base_ids, base_ids[:6], rng.choice(400, size=4)]).astype(np.int32)
+    base_ids = rng.choice(400, size=20, replace=False)
+    ids_a = np.concatenate([base_ids, base_ids[:4], rng.choice(400, size=3)]).astype(np.int32)
     w_a = rng.integers(0, 4, size=len(ids_a)).astype(np.float32)
     w_a[:3] = [1, 2, 3]
-    pad = rng.choice(400, size=70 - len(ids_a)).astype(np.int32)
-    ids_b = np.concatenate([ids_a, pad])
-    w_b = np.concatenate([w_a, np.zeros(len(pad), np.float32)])
-    assert len(ids_a) <= 64 < len(ids_b)
-    q = synth.Queries(q_ptr=np.array([0, len(ids_a), len(ids_a) + len(ids_b)]),
-                      ids=np.concatenate([ids_a, ids_b]), weights=np.concatenate([w_a, w_b]))
-    got = run(W, corpus_of(W, c), q, 10.0, 15)
+    qs = [(ids_a, w_a)]
+    for total in (50, 70):
+        pad = rng.choice(400, size=total - len(ids_a)).astype(np.int32)
+        qs.append((np.concatenate([ids_a, pad]), np.concatenate([w_a, np.zeros(len(pad), np.float32)])))
+    assert len(qs[0][0]) <= 32 < len(qs[1][0]) <= 64 < len(qs[2][0])
     ref = oracle_support(c, ids_a, w_a, 10.0, 15)
-    assert_close(got[0], ref, TOL32, "short query")
-    assert_close(got[1], ref, TOL32, "long query")
-    assert_close(got[1], got[0], 1e-5, "short vs long selection")
+    corpus = corpus_of(W, c)
+    for order in ((0, 1, 2), (2, 1, 0)):
+        q = synth.Queries(q_ptr=np.concatenate([[0], np.cumsum([len(qs[i][0]) for i in order])]),
+                          ids=np.concatenate([qs[i][0] for i in order]),
+                          weights=np.concatenate([qs[i][1] for i in order]))
+        for cd, tol in (("fp32", TOL32), ("bf16", TOL16)):
+            got = run(W, corpus, q, 10.0, 15, cdist=cd)
+            for b, i in enumerate(order):
+                assert_close(got[b], ref, tol, f"{cd} query of {len(qs[i][0])} entries at position {b}")
+                assert_close(got[b], got[order.index(0)], 1e-5 if cd == "fp32" else 1e-4,
+                             f"{cd} {len(qs[i][0])} vs {len(qs[0][0])} entries")
 
 
 def test_all_length_buckets_and_multiwave_items(W):
