@@ -472,6 +472,15 @@ def test_invalid_queries_are_nan_with_codes(W):
     assert list(codes) == [0, 1, 2, 3]
     o = out.cpu().numpy()
     assert np.all(np.isfinite(o[0])) and np.all(np.isnan(o[1:]))
+    # each query alone: a short single query is selected inside the cost-matrix kernel
+    for b in range(4):
+        one = W.QueryBatch.from_arrays(np.array([0, 2]), ids[2 * b:2 * b + 2], w[2 * b:2 * b + 2])
+        for cd in ("fp32", "bf16"):
+            row = corpus.query(one, 10.0, 15, cdist=cd, check=False).cpu().numpy()[0]
+            assert list(corpus.query_errors(corpus.last_workspace, 1)) == [b], f"query {b} alone, {cd}"
+            assert np.all(np.isfinite(row)) if b == 0 else np.all(np.isnan(row)), f"query {b} alone, {cd}"
+            if b == 0 and cd == "fp32":
+                assert_close(row, o[0], 1e-6, "query 0 alone vs in the batch")
 
 
 def test_corpus_validation_errors(W):
