@@ -293,8 +293,9 @@ __device__ __forceinline__ int64_t rec_begin(const int4& r) {
 // final pass in this launch), so the code for the other schedules and the
 // registers it needs are left out.  HALF (one-wave items, lg_cg <= 4): an
 // item spans 32 lanes and a wave holds two; no sum crosses lane bit 5.
+// first: this block's first document record, when the caller has read it.
 template <int TC, int TR, int LG_CG, int MAXW, bool RES, bool HALF = false>
-__device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk) {
+__device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk, const int4* first = nullptr) {
   static_assert(!HALF || (MAXW == 1 && LG_CG <= 4), "half-wave items are one-wave shapes");
   const bool load_u = !RES && p.load_u, store_u = !RES && p.store_u;
   const bool load_w = !RES && p.load_w, store_w = !RES && p.store_w;
@@ -320,7 +321,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
   for (int base = blk * items; base < p.ndocs; base += nblk * items) {
     const int item = base + slot;
     const bool active = item < p.ndocs;
-    const int4 rec = active ? p.drec[item] : make_int4(0, 0, 0, 0);
+    const int4 rec = first && base == blk * items ? *first : active ? p.drec[item] : make_int4(0, 0, 0, 0);
     const int64_t beg = rec_begin(rec);
     const int n = rec.z, k = rec.w;
 
@@ -639,6 +640,33 @@ __global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
   sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x);
 }
 
+// T rows per lane hold documents of up to (lanes per item >> lg_cg) * T
+// words.  A wave whose documents all fit in 3/4 of that runs a body of 3T/4
+// rows: the power-of-two length buckets leave the upper quarter of the rows
+// empty for most of their documents, and every row costs its cells' FMAs in
+// every iteration.  The choice is per wave (no sum crosses waves here), from
+// the document records the body would read first anyway.
+template <int TC, int T, int LG_CG, bool RES, bool HALF>
+__device__ __forceinline__ void sink_body_fit(const SinkParams& p, int blk, int nblk) {
+  if constexpr (T >= 4) {
+    constexpr int IL = HALF ? 32 : 64;
+    constexpr int T3 = 3 * T / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int items = (int)(blockDim.x >> 6) * (64 / IL);
+    const int item = blk * items + wave * (64 / IL) + (HALF ? lane >> 5 : 0);
+    const int4 rec = item < p.ndocs ? p.drec[item] : make_int4(0, 0, 0, 0);
+    int nmax = __builtin_amdgcn_readfirstlane(rec.z);
+    if constexpr (HALF) nmax = max(nmax, __builtin_amdgcn_readlane(rec.z, 32));
+    if (nmax <= (IL >> LG_CG) * T3) {
+      sink_body<TC, T3, LG_CG, 1, RES, HALF>(p, blk, nblk, &rec);
+    } else {
+      sink_body<TC, T, LG_CG, 1, RES, HALF>(p, blk, nblk, &rec);
+    }
+  } else {
+    sink_body<TC, T, LG_CG, 1, RES, HALF>(p, blk, nblk);
+  }
+}
+
 // One-wave items, four per block (eight as half-wave items), for several
 // length buckets of one query in a single launch.  Group g holds blocks
 // [end[g-1], end[g]) and documents drec[off[g]] ... drec[off[g] + ndocs[g] - 1];
@@ -673,24 +701,24 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
   if constexpr (LG_CG <= 4) {
     if (half) {
       if (shift == 0) {
-        sink_body<TC, TRMAX, LG_CG, 1, RES, true>(p, b - b0, b1 - b0);
+        sink_body_fit<TC, TRMAX, LG_CG, RES, true>(p, b - b0, b1 - b0);
       } else if constexpr (TRMAX >= 2) {
         if (shift == 1) {
-          sink_body<TC, TRMAX / 2, LG_CG, 1, RES, true>(p, b - b0, b1 - b0);
+          sink_body_fit<TC, TRMAX / 2, LG_CG, RES, true>(p, b - b0, b1 - b0);
         } else if constexpr (TRMAX >= 4) {
-          sink_body<TC, TRMAX / 4, LG_CG, 1, RES, true>(p, b - b0, b1 - b0);
+          sink_body_fit<TC, TRMAX / 4, LG_CG, RES, true>(p, b - b0, b1 - b0);
         }
       }
       return;
     }
   }
   if (shift == 0) {
-    sink_body<TC, TRMAX, LG_CG, 1, RES>(p, b - b0, b1 - b0);
+    sink_body_fit<TC, TRMAX, LG_CG, RES, false>(p, b - b0, b1 - b0);
   } else if constexpr (TRMAX >= 2) {
     if (shift == 1) {
-      sink_body<TC, TRMAX / 2, LG_CG, 1, RES>(p, b - b0, b1 - b0);
+      sink_body_fit<TC, TRMAX / 2, LG_CG, RES, false>(p, b - b0, b1 - b0);
     } else if constexpr (TRMAX >= 4) {
-      sink_body<TC, TRMAX / 4, LG_CG, 1, RES>(p, b - b0, b1 - b0);
+      sink_body_fit<TC, TRMAX / 4, LG_CG, RES, false>(p, b - b0, b1 - b0);
     }
   }
 }
