@@ -634,9 +634,26 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
   }
 }
 
-// Multi-wave items: one item per block of up to MAXW waves.
+// Multi-wave items: one item per block of up to MAXW waves.  When the grid
+// has a block per document, a block whose document fits in 3/4 of its rows
+// runs a body of 3TR/4 rows per lane (see sink_body_fit); the choice is the
+// same for every wave of the block, so its barriers stay matched.
 template <int TC, int TR, int LG_CG, int MAXW, bool RES>
 __global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
+  if constexpr (TR >= 4) {
+    if ((int)gridDim.x >= p.ndocs) {
+      constexpr int T3 = 3 * TR / 4;
+      const int item = blockIdx.x;
+      const int4 rec = item < p.ndocs ? p.drec[item] : make_int4(0, 0, 0, 0);
+      const int rows = (int)(blockDim.x >> 6) * (64 >> LG_CG) * T3;
+      if (rec.z <= rows) {
+        sink_body<TC, T3, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x, &rec);
+      } else {
+        sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x, &rec);
+      }
+      return;
+    }
+  }
   sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x);
 }
 
@@ -657,7 +674,9 @@ __device__ __forceinline__ void sink_body_fit(const SinkParams& p, int blk, int 
     const int4 rec = item < p.ndocs ? p.drec[item] : make_int4(0, 0, 0, 0);
     int nmax = __builtin_amdgcn_readfirstlane(rec.z);
     if constexpr (HALF) nmax = max(nmax, __builtin_amdgcn_readlane(rec.z, 32));
-    if (nmax <= (IL >> LG_CG) * T3) {
+    // only when the grid takes every document in one pass (the body keeps
+    // its row count for all the items it walks)
+    if (nmax <= (IL >> LG_CG) * T3 && nblk * items >= p.ndocs) {
       sink_body<TC, T3, LG_CG, 1, RES, HALF>(p, blk, nblk, &rec);
     } else {
       sink_body<TC, T, LG_CG, 1, RES, HALF>(p, blk, nblk, &rec);
