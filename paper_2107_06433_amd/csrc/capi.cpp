@@ -223,6 +223,13 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
     lists[b].push_back((int)k);
     c->bucket_nnz[b] += len;
   }
+  // longest documents first inside a bucket (ties by id): the items that take
+  // longest start first, and the two documents of a half-wave item have
+  // similar lengths, so a smaller row body fits both more often
+  for (int b = 0; b < kNumBuckets; ++b)
+    std::stable_sort(lists[b].begin(), lists[b].end(), [&](int x, int y) {
+      return ptr[(size_t)x + 1] - ptr[(size_t)x] > ptr[(size_t)y + 1] - ptr[(size_t)y];
+    });
   std::vector<int> flat;
   flat.reserve((size_t)D.N);
   for (int b = 0; b <= kNumBuckets; ++b) {
