@@ -164,8 +164,10 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
                                  int32_t schedule);
 
 /* Enqueues the whole hot path for B queries on `stream` and returns without
- * waiting: query selection, cost matrix + K (one GEMM over all queries),
- * the Sinkhorn iterations and the final pass.  `out` (device, B*N float32,
+ * waiting: query selection, cost matrix + K (one GEMM over all queries;
+ * a call with one query of at most 64 entries, at most 32 padded columns and
+ * an embedding width of at most 384 (f32) or 768 (bf16) selects it inside
+ * the GEMM's launch), the Sinkhorn iterations and the final pass.  `out` (device, B*N float32,
  * row b = query b) is written when the stream reaches the end of the call.
  * Host-side argument errors are reported synchronously.  Errors found on the
  * device (a query id outside [0, V), a negative or non-finite weight, no
