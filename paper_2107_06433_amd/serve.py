@@ -72,40 +72,70 @@ class Scheduler:
         return req.future
 
     def poll(self, now: float) -> int:
-        """Resolve finished batches; returns how many requests completed."""
+        """Resolve finished batches; returns how many requests completed.
+
+        A batch whose executor fails (while asking whether it is done or for
+        its results) resolves every one of its requests with that exception;
+        its memory returns to the budget either way.
+        """
         n = 0
         still = []
         for b in self.inflight:
-            if self.ex.done(b.handle):
-                for req, res in zip(b.requests, self.ex.results(b.handle)):
-                    req.done = now
-                    if isinstance(res, Exception):
-                        req.future.set_exception(res)
-                    else:
-                        req.future.set_result(res)
-                    self.completed.append(req)
-                    n += 1
+            try:
+                if not self.ex.done(b.handle):
+                    still.append(b)
+                    continue
+                results = self.ex.results(b.handle)
+            except Exception as e:  # noqa: BLE001 - handed to the callers' futures
+                results = [e] * len(b.requests)
+            for req, res in zip(b.requests, results):
+                req.done = now
+                if isinstance(res, Exception):
+                    req.future.set_exception(res)
+                else:
+                    req.future.set_result(res)
+                self.completed.append(req)
+                n += 1
+            try:
                 self.ex.release(b.handle)
+            finally:
                 self.used -= b.nbytes
-            else:
-                still.append(b)
         self.inflight = still
         return n
 
+    def _fail(self, req: Request, now: float, exc: Exception) -> None:
+        req.done = now
+        req.future.set_exception(exc)
+        self.rejected.append(req)
+
     def admit(self, now: float) -> int:
-        """Launch batches while slots and memory allow; returns requests admitted."""
+        """Launch batches while slots and memory allow; returns requests admitted.
+
+        A request whose cost the executor cannot compute (an invalid query) is
+        rejected with that exception; a batch whose launch fails resolves its
+        requests with the launch's exception and takes no memory.
+        """
         admitted = 0
         while self.pending and len(self.inflight) < self.max_inflight:
             take, nbytes = [], 0
             while self.pending and len(take) < self.max_batch:
                 cand = take + [self.pending[0]]
-                need = self.ex.cost(cand)
+                try:
+                    need = self.ex.cost(cand)
+                except Exception as e:  # noqa: BLE001
+                    if take:
+                        try:  # is the newcomer the problem? check it alone
+                            self.ex.cost(cand[-1:])
+                        except Exception as e1:  # noqa: BLE001
+                            self._fail(self.pending.popleft(), now, e1)
+                            continue
+                        break  # it is valid alone: launch what we have, retry it next time
+                    self._fail(self.pending.popleft(), now, e)
+                    continue
                 if need > self.budget and not take:
                     req = self.pending.popleft()  # can never fit, even alone
-                    req.done = now
-                    req.future.set_exception(RejectedError(
+                    self._fail(req, now, RejectedError(
                         f"request {req.rid} needs {need} bytes, budget is {self.budget}"))
-                    self.rejected.append(req)
                     continue
                 if self.used + need > self.budget:
                     break
@@ -116,7 +146,12 @@ class Scheduler:
             for r in take:
                 r.admitted = now
             b = Batch(requests=take, nbytes=nbytes, launched=now)
-            b.handle = self.ex.launch(take)
+            try:
+                b.handle = self.ex.launch(take)
+            except Exception as e:  # noqa: BLE001
+                for r in take:
+                    self._fail(r, now, e)
+                continue
             self.inflight.append(b)
             self.used += nbytes
             self.peak_used = max(self.peak_used, self.used)
@@ -157,6 +192,10 @@ class GpuExecutor:
         return ptr
 
     def cost(self, reqs) -> int:
+        for r in reqs:
+            if len(r.ids) > self.wmd.MAX_QUERY_LEN:
+                raise self.wmd.WMDError(4, f"a query has {len(r.ids)} entries, at most "
+                                           f"{self.wmd.MAX_QUERY_LEN} are supported")
         ptr = self._ptr(reqs)
         key = (len(reqs), int(((np.diff(ptr) + 3) // 4).sum()))  # workspace depends on B and sum of widths
         n = self._cost_cache.get(key)
@@ -217,8 +256,11 @@ class Server:
     """Background-thread server: submit() returns a Future of the distances."""
 
     def __init__(self, corpus, lam: float, max_iter: int, cdist: str = "bf16", mem_budget: int = 8 << 30,
-                 max_batch: int = 64, max_inflight: int = 3):
-        self.ex = GpuExecutor(corpus, lam, max_iter, cdist, streams=max_inflight)
+                 max_batch: int = 64, max_inflight: int = 3, executor=None, max_query_len: int = 2048):
+        # executor: a stand-in for the GPU executor (tests); corpus is then unused
+        self.ex = executor if executor is not None else GpuExecutor(corpus, lam, max_iter, cdist,
+                                                                    streams=max_inflight)
+        self.max_query_len = int(max_query_len)
         self.sched = Scheduler(self.ex, mem_budget, max_batch, max_inflight)
         self._lock = threading.Lock()
         self._stop = threading.Event()
@@ -230,10 +272,18 @@ class Server:
         return time.perf_counter() - self._t0
 
     def submit(self, ids, weights) -> Future:
-        ids = np.asarray(ids, dtype=np.int32)
-        weights = np.asarray(weights, dtype=np.float32)
+        """Queue one query; malformed or oversized queries get a failed Future."""
+        ids = np.asarray(ids, dtype=np.int32).ravel()
+        weights = np.asarray(weights, dtype=np.float32).ravel()
         if ids.size == 0 or ids.shape != weights.shape:
-            raise ValueError("a query needs matching, non-empty ids and weights")
+            f: Future = Future()
+            f.set_exception(ValueError("a query needs matching, non-empty ids and weights"))
+            return f
+        if ids.size > self.max_query_len:
+            f = Future()
+            f.set_exception(ValueError(f"a query has {ids.size} entries, at most {self.max_query_len} "
+                                       "are supported"))
+            return f
         req = Request(ids=ids, weights=weights, arrival=self._clock())
         with self._lock:
             return self.sched.submit(req)
@@ -242,8 +292,12 @@ class Server:
         while not self._stop.is_set() or self.sched.pending or self.sched.inflight:
             with self._lock:
                 now = self._clock()
-                self.sched.poll(now)
-                self.sched.admit(now)
+                try:
+                    self.sched.poll(now)
+                    self.sched.admit(now)
+                except Exception as e:  # noqa: BLE001 - keep serving; fail what is queued
+                    while self.sched.pending:
+                        self.sched._fail(self.sched.pending.popleft(), now, e)
                 idle = not self.sched.pending and not self.sched.inflight
             time.sleep(0.001 if idle else 0.00005)
 

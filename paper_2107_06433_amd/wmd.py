@@ -23,6 +23,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "device e
 CDIST = {"fp32": 0, "bf16": 1}
 SCHEDULE = {"auto": 0, "resident": 1, "per_iteration": 2, "unfused": 3}
 QUERY_GRAPH = 1
+MAX_QUERY_LEN = 2048     # raw entries per query the library accepts
+MAX_DOC_LEN = 4096       # entries per document
 QUERY_ERRORS = {0: "ok", 1: "query word id out of range", 2: "query weight negative or not finite",
                 3: "query has no positive weight", 4: "query too long"}
 

@@ -118,3 +118,92 @@ def test_drain_finishes_in_flight_work():
     sch.drain(tick)
     assert all(f.done() for f in futs) and not sch.inflight and sch.used == 0
     assert sch.batches == 3
+
+
+class FailingExecutor(FakeExecutor):
+    """Fails in cost() for queries holding word id 666, in launch() for id 777
+    and while polling a batch that holds id 888."""
+
+    def cost(self, reqs):
+        if any(666 in r.ids for r in reqs):
+            raise ValueError("bad query")
+        return super().cost(reqs)
+
+    def launch(self, reqs):
+        if any(777 in r.ids for r in reqs):
+            raise RuntimeError("launch failed")
+        h = super().launch(reqs)
+        h["boom"] = any(888 in r.ids for r in reqs)
+        return h
+
+    def done(self, h):
+        if h["boom"]:
+            raise RuntimeError("device error")
+        return super().done(h)
+
+
+def test_executor_errors_resolve_futures_and_keep_the_budget():
+    clock = Clock()
+    ex = FailingExecutor(clock, delay=0.5)
+    sch = Scheduler(ex, mem_budget=10_000, max_batch=1, max_inflight=2)
+    ok1 = sch.submit(req(2))
+    bad_cost = sch.submit(Request(ids=np.array([1, 666], np.int32), weights=np.ones(2, np.float32), arrival=0.0))
+    bad_launch = sch.submit(Request(ids=np.array([777], np.int32), weights=np.ones(1, np.float32), arrival=0.0))
+    bad_poll = sch.submit(Request(ids=np.array([888], np.int32), weights=np.ones(1, np.float32), arrival=0.0))
+    ok2 = sch.submit(req(3, 10))
+    for step in range(10):
+        clock.t = 0.5 * step
+        sch.poll(clock.t)
+        sch.admit(clock.t)
+    assert ok1.result(timeout=0) == 1 and ok2.result(timeout=0) == 33
+    with pytest.raises(ValueError):
+        bad_cost.result(timeout=0)
+    with pytest.raises(RuntimeError, match="launch failed"):
+        bad_launch.result(timeout=0)
+    with pytest.raises(RuntimeError, match="device error"):
+        bad_poll.result(timeout=0)
+    assert sch.used == 0 and not sch.inflight and not sch.pending
+
+
+def test_invalid_newcomer_does_not_block_a_forming_batch():
+    clock = Clock()
+    ex = FailingExecutor(clock, delay=0.1)
+    sch = Scheduler(ex, mem_budget=10_000, max_batch=4, max_inflight=1)
+    a = sch.submit(req(2))
+    bad = sch.submit(Request(ids=np.array([666], np.int32), weights=np.ones(1, np.float32), arrival=0.0))
+    b = sch.submit(req(2, 5))
+    sch.admit(0.0)
+    assert ex.launched == [[0, 2]]
+    with pytest.raises(ValueError):
+        bad.result(timeout=0)
+    clock.t = 1.0
+    sch.poll(1.0)
+    assert a.result(timeout=0) == 1 and b.result(timeout=0) == 11
+
+
+def test_server_thread_survives_failures_and_rejects_oversized_queries():
+    import time as _time
+
+    from paper_2107_06433_amd.serve import Server
+
+    class WallExecutor(FailingExecutor):
+        def __init__(self):
+            super().__init__(_time.perf_counter, delay=0.01)
+
+    srv = Server(None, 10.0, 15, executor=WallExecutor(), mem_budget=10_000, max_batch=1, max_inflight=2,
+                 max_query_len=8)
+    too_long = srv.submit(np.arange(9), np.ones(9))
+    empty = srv.submit([], [])
+    bad = srv.submit([666], [1.0])
+    boom = srv.submit([777], [1.0])
+    good = [srv.submit(np.arange(i, i + 3), np.ones(3)) for i in range(5)]
+    srv.close()
+    with pytest.raises(ValueError, match="at most 8"):
+        too_long.result(timeout=5)
+    with pytest.raises(ValueError):
+        empty.result(timeout=5)
+    with pytest.raises(ValueError):
+        bad.result(timeout=5)
+    with pytest.raises(RuntimeError):
+        boom.result(timeout=5)
+    assert [f.result(timeout=5) for f in good] == [3 * i + 3 for i in range(5)]
