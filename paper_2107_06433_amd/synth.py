@@ -54,7 +54,11 @@ def unique_bags(rng: np.random.Generator, cdf: np.ndarray, lengths: np.ndarray):
     """Draw len(lengths) bags of unique Zipf ids; bag i has lengths[i] ids.
 
     Returns (ptr int64[n_bags+1], ids int32[total]) with ids ascending in each bag.
-    Duplicates inside a bag are redrawn until none remain.
+    Duplicates inside a bag are redrawn until none remain: each round finds,
+    in (bag, id, position) order, every entry that repeats an earlier one of
+    its bag and draws new ids for them in that order.  Only the bags that had
+    a repeat can have one in the next round, so later rounds look at those
+    bags alone (the draws are the same as re-examining every bag).
     """
     lengths = np.asarray(lengths, dtype=np.int64)
     ptr = np.zeros(len(lengths) + 1, dtype=np.int64)
@@ -62,14 +66,19 @@ def unique_bags(rng: np.random.Generator, cdf: np.ndarray, lengths: np.ndarray):
     total = int(ptr[-1])
     bag = np.repeat(np.arange(len(lengths), dtype=np.int64), lengths)
     ids = _draw_ids(rng, cdf, total)
-    while True:
-        order = np.lexsort((ids, bag))
-        sb, si = bag[order], ids[order]
+    live = np.arange(total, dtype=np.int64)  # positions examined this round, ascending
+    while live.size:
+        lb, li = bag[live], ids[live]
+        order = np.lexsort((li, lb))
+        sb, si = lb[order], li[order]
         dup = (sb[1:] == sb[:-1]) & (si[1:] == si[:-1])
         if not dup.any():
             break
-        pos = order[1:][dup]
+        pos = live[order[1:][dup]]
         ids[pos] = _draw_ids(rng, cdf, len(pos))
+        hit = np.zeros(len(lengths), dtype=bool)
+        hit[bag[pos]] = True
+        live = np.nonzero(hit[bag])[0]
     order = np.lexsort((ids, bag))
     return ptr, ids[order].astype(np.int32)
 
