@@ -135,7 +135,15 @@ typedef struct {
   const int64_t* q_ptr;       /* device copy of q_ptr_host                             */
   const int32_t* q_ids;       /* device, q_ptr[B] word ids                             */
   const float* q_weights;     /* device, q_ptr[B] weights                              */
-  float lambda;               /* entropic weight, finite, > 0: K = exp(-lambda M)      */
+  float lambda;               /* entropic weight, finite, > 0: K = exp(-lambda M).
+                                 Range: K is float32 and is not rescaled (the paper's
+                                 iteration has no log-domain form).  While every
+                                 document word has some query word with lambda M below
+                                 about 87 (exp above the smallest normal float) the
+                                 results keep float32 accuracy; a document with a word
+                                 whose whole row of K underflows scores +Inf (below).
+                                 With N(0, 1/d) embeddings, where distinct words lie
+                                 about 1.0-1.5 apart, that holds up to lambda ~ 60.     */
   int32_t max_iter;           /* Sinkhorn-Knopp iterations, 0..100000                  */
   int32_t cdist;              /* wmd_cdist                                             */
   int32_t schedule;           /* wmd_schedule                                          */
@@ -164,7 +172,7 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
                                  int32_t schedule);
 
 /* Enqueues the whole hot path for B queries on `stream` and returns without
- * waiting: query selection, cost matrix + K (one GEMM over all queries;
+ * waiting (Algorithm 1 for every query against every document): query selection, cost matrix + K (one GEMM over all queries;
  * a call with one query of at most 64 entries, at most 32 padded columns and
  * an embedding width of at most 384 (f32) or 768 (bf16) selects it inside
  * the GEMM's launch), the Sinkhorn iterations and the final pass.  `out` (device, B*N float32,
@@ -172,7 +180,10 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
  * Host-side argument errors are reported synchronously.  Errors found on the
  * device (a query id outside [0, V), a negative or non-finite weight, no
  * positive weight) make that query's row NaN and are read back with
- * wmd_query_errors().  The workspace must be 256-byte aligned.  Calls that
+ * wmd_query_errors().  Per document: a finite distance; NaN for a document
+ * without positive weight or a row of an invalid query; +Inf where the float32
+ * scaling broke down for a document with words (K underflow, see lambda).
+ * The workspace must be 256-byte aligned.  Calls that
  * share a workspace must be ordered on one stream; calls with separate
  * workspaces may run concurrently. */
 wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,

@@ -356,7 +356,8 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
   sp.q_ptr = q->q_ptr; sp.q_ids = q->q_ids; sp.q_w = q->q_weights;
   sp.B = q->B; sp.V = c->V; sp.d = c->d; sp.dp = c->dp; sp.emb = c->emb;
   sp.err = at<int>(ws, L.err); sp.vr = at<int>(ws, L.vr); sp.qid = at<int>(ws, L.qid);
-  sp.r = at<float>(ws, L.r); sp.cinfo = at<int2>(ws, L.cinfo); sp.qn = at<float>(ws, L.qn);
+  sp.r = at<float>(ws, L.r); sp.cinfo = at<int2>(ws, L.cinfo); sp.qinfo = at<int2>(ws, L.qinfo);
+  sp.qn = at<float>(ws, L.qn);
   sp.q32 = at<float>(ws, L.q32); sp.q16 = at<uint16_t>(ws, L.q16);
   sp.want_bf16 = q->cdist == WMD_CDIST_BF16;
   c->tag_query = -1; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = 0;
@@ -371,6 +372,9 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
   cp.used = at<int>(c->ws, CL.used); cp.U = c->U;
   cp.q32 = sp.q32; cp.q16 = sp.q16; cp.qn = sp.qn; cp.qid = sp.qid; cp.cinfo = sp.cinfo;
   cp.C = plan.C; cp.dp = c->dp; cp.lam = q->lambda; cp.kt = kt;
+  float* km = at<float>(ws, L.km);
+  cp.km = km;
+  cp.one_query = q->B == 1;
   // one short query whose cost matrix takes the skinny kernel: that kernel
   // selects the query itself (no separate launch, the selection's latency
   // hidden behind the vocabulary stream)
@@ -393,8 +397,16 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
     // the tile shape is picked inside the launch; its name is filled in afterwards
     const char* name = "cdist_kernel";
     const size_t nrec = c->recs.size();
-    WMD_HIP(timed_launch(c, s, "", flops, bytes, [&] { return launch_cdist(cp, bf16, s, &name); }));
+    bool shifted = false;
+    WMD_HIP(timed_launch(c, s, "", flops, bytes, [&] { return launch_cdist(cp, bf16, s, &name, &shifted); }));
     if (c->recs.size() > nrec) c->recs.back().name = std::string(name) + (fuse ? "+select" : "");
+    if (!shifted) {
+      // row shifts of K^T: read the distances, write K and one shift per row
+      const double cells = U * (double)plan.C;
+      WMD_HIP(timed_launch(c, s, "gibbs_rows_kernel", 2.0 * cells, 8.0 * cells + 4.0 * U * q->B, [&] {
+        return launch_gibbs_rows(kt, km, sp.qinfo, c->U, q->B, q->lambda, s);
+      }));
+    }
   }
 
   // iterations per document: 0 for documents that are never iterated (no
@@ -493,6 +505,7 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
     float* orow = out + (size_t)b * (size_t)c->N;
     SinkParams p{};
     p.kt = kt + (size_t)col0 * (size_t)c->U;
+    p.km = km + (size_t)b * (size_t)c->U;
     p.r = sp.r + col0;
     p.vr = sp.vr + b;
     p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);

@@ -218,8 +218,10 @@ __global__ void __launch_bounds__(256) cdist_kernel(CdistParams p) {
         const int64_t m = m0 + wm * T::TM + a * 16 + 4 * (lane >> 4) + i;
         const float m2 = enr[i] + qnc[b] - 2.f * acc[a][b][i];
         const float dist = usr[i] == qc[b] ? 0.f : sqrtf(fmaxf(m2, 0.f));
-        // an unused query slot holds K = 1: padding for the Sinkhorn kernels
-        const float kv = qc[b] >= 0 ? expf(-p.lam * dist) : 1.f;
+        // distances; gibbs_rows_kernel turns them into the row-scaled K (an
+        // unused query slot, +inf here, becomes K = 1: padding for the
+        // Sinkhorn kernels)
+        const float kv = qc[b] >= 0 ? dist : __int_as_float(0x7F800000);
         if (n < p.C && m < p.U) kt[(size_t)m * cic[b].y] = kv;
       }
     }
@@ -519,22 +521,71 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   for (int u = 0; u < N4; ++u)
     k4[u] = sum_scatter32(sum_scatter16(acc4[u][0], acc4[u][1]), sum_scatter16(acc4[u][2], acc4[u][3]));
   // epilogue: register i of lane l holds row 4*(l/16)+i, column l%16 of each
-  // tile.  All K values first, then the stores (a store counts against the
+  // tile.  All values first, then the stores (a store counts against the
   // same memory counter as a load; nothing waits on them).
+  constexpr float kInf = __builtin_huge_valf();
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float m2 = en_r[i] + qn_c[t] - 2.f * acc[t][i];
       const float dist = used_r[i] == q_c[t] ? 0.f : sqrtf(fmaxf(m2, 0.f));
-      // an unused query slot holds K = 1: padding for the Sinkhorn kernels
-      acc[t][i] = q_c[t] >= 0 ? expf(-p.lam * dist) : 1.f;
+      // an unused query slot: +inf; so is a column past C (never stored, and
+      // with a selected query its Q row is zero, not a copy of a real one),
+      // which keeps both out of the row minima below
+      acc[t][i] = q_c[t] >= 0 && t * 16 + (lane & 15) < p.C ? dist : kInf;
     }
 #pragma unroll
   for (int u = 0; u < N4; ++u) {
     const float m2 = en_4 + qn_4[u] - 2.f * k4[u];
     const float dist = used_4 == q_4[u] ? 0.f : sqrtf(fmaxf(m2, 0.f));
-    k4[u] = q_4[u] >= 0 ? expf(-p.lam * dist) : 1.f;
+    k4[u] = q_4[u] >= 0 && NT * 16 + 4 * u + (lane & 3) < p.C ? dist : kInf;
+  }
+  // One query in the call: every column belongs to it, so each row's shift
+  // m_j is the minimum over the row's columns (over the tiles, then over the
+  // 16 lanes that hold a tile row; over the 4-column groups, then over the 4
+  // lanes that hold a group row), the two layouts exchanging their row minima
+  // through lane reads.  Rows then hold K = exp(-lambda (M - m_j)) and an
+  // unused slot K = 1.  Otherwise the distances are stored as they are.
+  const bool shift = p.one_query != 0;
+  float rmin[4] = {kInf, kInf, kInf, kInf};  // tile layout: row 4 (l >> 4) + i
+  float rmin4 = kInf;                        // group layout: row 4 ((l >> 2) & 3) + (l >> 4)
+  if (shift) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) rmin[i] = fminf(rmin[i], acc[t][i]);
+      if constexpr (NT > 0) rmin[i] = min_low<4>(rmin[i]);
+    }
+#pragma unroll
+    for (int u = 0; u < N4; ++u) rmin4 = fminf(rmin4, k4[u]);
+    if constexpr (N4 > 0) rmin4 = min_low<2>(rmin4);
+    if constexpr (NT > 0 && N4 > 0) {
+      // tile row 4g + i is group row (a, b) = (g, i), held by lane 16 i + 4 g;
+      // group row (a, b) is tile row 4a + b, register b of lane 16 a
+      const int g = lane >> 4, a = (lane >> 2) & 3;
+      float from4[4], fromt[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        from4[i] = __shfl(rmin4, 16 * i + 4 * g);
+        fromt[i] = __shfl(rmin[i], 16 * a);
+      }
+      const float tb = g == 0 ? fromt[0] : g == 1 ? fromt[1] : g == 2 ? fromt[2] : fromt[3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rmin[i] = fminf(rmin[i], from4[i]);
+      rmin4 = fminf(rmin4, tb);
+    }
+    // a row with no used column (an invalid query): no shift, K = 1
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rmin[i] = rmin[i] < kInf ? rmin[i] : 0.f;
+    rmin4 = rmin4 < kInf ? rmin4 : 0.f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[t][i] = acc[t][i] < kInf ? expf(-p.lam * (acc[t][i] - rmin[i])) : 1.f;
+#pragma unroll
+    for (int u = 0; u < N4; ++u) k4[u] = k4[u] < kInf ? expf(-p.lam * (k4[u] - rmin4)) : 1.f;
   }
 #pragma unroll
   for (int u = 0; u < N4; ++u) {
@@ -550,6 +601,19 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     for (int i = 0; i < 4; ++i) {
       const int64_t m = m0 + 4 * (lane >> 4) + i;
       if (n < p.C && m < p.U) kt[(size_t)m * ci_c[t].y] = acc[t][i];
+    }
+  }
+  if (shift) {
+    if constexpr (NT > 0) {
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t m = m0 + 4 * (lane >> 4) + i;
+          if (m < p.U) p.km[m] = rmin[i];
+        }
+      }
+    } else {
+      if ((lane & 3) == 0 && m4 < p.U) p.km[m4] = rmin4;
     }
   }
 }
@@ -625,11 +689,14 @@ static bool skinny_fits(const CdistParams& p, bool bf16) {
 
 bool cdist_fuses_select(const CdistParams& p, bool bf16) { return p.U > 0 && p.C > 0 && skinny_fits(p, bf16); }
 
-hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name) {
+hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name, bool* shifted) {
+  *shifted = false;
   if (p.U <= 0 || p.C <= 0) return hipSuccess;
-  if (p.sel_n > 0 && (!cdist_fuses_select(p, bf16) || p.sel_n > 64 || p.C != ((p.sel_n + 3) & ~3)))
+  if (p.sel_n > 0 && (!cdist_fuses_select(p, bf16) || p.sel_n > 64 || p.C != ((p.sel_n + 3) & ~3) ||
+                      !p.one_query))
     return hipErrorInvalidValue;
   const bool skinny = skinny_fits(p, bf16);
+  *shifted = skinny && p.one_query;
   if (skinny && !bf16 && p.C <= 32) return run_skinny_f32(p, s, name);
   if (skinny && p.C <= 16) {
     *name = "cdist_skinny_kernel<1,0,1>";
@@ -649,6 +716,58 @@ hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const ch
   }
   *name = bf16 ? "cdist_kernel<128,128,2,1,32>" : "cdist_kernel<128,128,2,0,16>";
   return bf16 ? run<128, 128, 2, true, 32>(p, s) : run<128, 128, 2, false, 16>(p, s);
+}
+
+// Row shift for calls whose cost-matrix kernel stored plain distances (see
+// CdistParams): per query b and row j, m_j = min over the query's columns,
+// K = exp(-lambda (M - m_j)), +inf (an unused slot) -> 1.  A row of S floats
+// takes L = S/4 lanes rounded up to a power of two (at most 64, then the lanes
+// loop over the row), one 16-byte piece per lane and step; 64 / L rows per
+// wave.
+__global__ void __launch_bounds__(256) gibbs_rows_kernel(float* kt, float* km, const int2* qinfo, int64_t U,
+                                                        float lam) {
+  const int b = blockIdx.y;
+  const int2 qi = qinfo[b];
+  const int S = qi.y;
+  const int n4 = S >> 2;
+  int lg = 0;
+  while ((1 << lg) < n4 && lg < 6) ++lg;
+  const int L = 1 << lg, R = 64 >> lg;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane & (L - 1), rw = lane >> lg;
+  float* blk = kt + (size_t)qi.x * (size_t)U;
+  constexpr float kInf = __builtin_huge_valf();
+  for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * R; r0 < U; r0 += (int64_t)gridDim.x * 4 * R) {
+    const int64_t row = r0 + rw;
+    const bool ok = row < U;
+    float4* rp = (float4*)(blk + (size_t)(ok ? row : 0) * S);
+    float mn = kInf;
+    for (int c = sub; c < n4; c += L) {
+      const float4 v = rp[c];
+      mn = fminf(fminf(mn, v.x), fminf(v.y, fminf(v.z, v.w)));
+    }
+    for (int o = 1; o < L; o <<= 1) mn = fminf(mn, __shfl_xor(mn, o));
+    mn = mn < kInf ? mn : 0.f;
+    if (ok) {
+      for (int c = sub; c < n4; c += L) {
+        float4 v = rp[c];
+        v.x = v.x < kInf ? expf(-lam * (v.x - mn)) : 1.f;
+        v.y = v.y < kInf ? expf(-lam * (v.y - mn)) : 1.f;
+        v.z = v.z < kInf ? expf(-lam * (v.z - mn)) : 1.f;
+        v.w = v.w < kInf ? expf(-lam * (v.w - mn)) : 1.f;
+        rp[c] = v;
+      }
+      if (sub == 0) km[(size_t)b * (size_t)U + row] = mn;
+    }
+  }
+}
+
+hipError_t launch_gibbs_rows(float* kt, float* km, const int2* qinfo, int64_t U, int B, float lam, hipStream_t s) {
+  if (U <= 0 || B <= 0) return hipSuccess;
+  const int64_t gx = (U + 255) / 256;
+  dim3 grid((unsigned)(gx < 4096 ? gx : 4096), (unsigned)B);
+  gibbs_rows_kernel<<<grid, 256, 0, s>>>(kt, km, qinfo, U, lam);
+  return hipGetLastError();
 }
 
 }  // namespace wmd

@@ -111,6 +111,18 @@ __device__ __forceinline__ float sum_mid_bits(float x, int lo, int hi) {
   return x;
 }
 
+// Minimum over lane bits [0, NB) (NB <= 4), lower bits first, every lane of
+// the group receiving it.
+template <int NB>
+__device__ __forceinline__ float min_low(float x) {
+  if constexpr (NB > 0) x = fminf(x, dpp<kDppXor1>(x));
+  if constexpr (NB > 1) x = fminf(x, dpp<kDppXor2>(x));
+  if constexpr (NB > 2) x = fminf(x, dpp<kDppHalfMirror>(x));
+  if constexpr (NB > 3) x = fminf(x, dpp<kDppMirror>(x));
+  static_assert(NB <= 4, "within a 16-lane row");
+  return x;
+}
+
 // float -> bf16 bits, round to nearest even (inputs are finite).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   uint32_t u = __float_as_uint(f);

@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelectParams p) {
   if (t == 0) {
     p.err[b] = err & 1 ? 1 : err & 2 ? 2 : err & 4 ? 4 : err & 8 ? 3 : 0;
     p.vr[b] = vr;
+    p.qinfo[b] = make_int2((int)col0, S);
   }
   for (int s = t; s < S; s += 256) {
     const int i = s < vr && s < kMaxQueryLen ? s_slot[s] : -1;

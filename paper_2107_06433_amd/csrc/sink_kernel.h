@@ -272,9 +272,9 @@ __device__ __forceinline__ float max_low(float x) {
   return x;
 }
 
-// The cost M of a kernel entry K = exp(-lambda M) is -ln(K) / lambda =
-// log2(K) * (-ln 2 / lambda).  The final pass sums K u log2(K) and applies the
-// constant once per document.  The smallest normal float is added first: it
+// The cost M of a kernel entry K = exp(-lambda (M - m_j)) of a row-scaled row
+// is m_j - ln(K) / lambda = m_j + log2(K) * (-ln 2 / lambda).  The final pass
+// sums K u log2(K) per row and applies the constant once per lane.  The smallest normal float is added first: it
 // leaves every K >= 2^-102 unchanged (K = 1, a padding entry, gives exactly
 // 0) and turns K = 0 (an underflowed entry) into K u * (-126) = 0 instead of
 // 0 * inf.  One add, where a clamp with fmaxf costs two instructions.
@@ -282,6 +282,16 @@ __device__ __forceinline__ float log2_gibbs(float k) {
   return __builtin_amdgcn_logf(k + 1.17549435e-38f);
 }
 constexpr float kNegLn2 = -0.693147180559945309f;
+
+// A document with words always ends with a finite distance in exact
+// arithmetic.  In float32 a row of K underflows to 0 once lambda M exceeds
+// about 87-103 for every query word of that document word; its dot product is
+// then 0, w = c / 0 is infinite and the sums turn NaN.  Such a distance is
+// reported as +Inf, which keeps it apart from the NaN of an empty document or
+// an invalid query.
+__device__ __forceinline__ float flag_range(float d) {
+  return fabsf(d) <= 3.40282347e38f ? d : __int_as_float(0x7F800000);
+}
 
 __device__ __forceinline__ int64_t rec_begin(const int4& r) {
   return (int64_t)(uint32_t)r.x | ((int64_t)r.y << 32);
@@ -344,6 +354,14 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       const float c = j < n ? p.wn[beg + j] : 0.f;
       wid[t] = c > 0.f ? id : -1;
       cw[t] = c > 0.f ? c : 0.f;
+    }
+    // sum_j c_j m_j of this lane's rows (column lane 0 of each row adds it):
+    // the part of d_k that the row scaling of K^T took out of the stored rows
+    float cm = 0.f;
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      const float mj = p.km[wid[t] < 0 ? 0 : wid[t]];
+      cm = fmaf(cg == 0 ? cw[t] : 0.f, mj, cm);
     }
     // Columns of lane cg: the 4-column chunks cg, cg + CG, ... (4 TC4 columns,
     // one 16-byte load per row each: S and every K^T row start are multiples
@@ -614,6 +632,8 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       float part[1] = {0.f};
 #pragma unroll
       for (int t = 0; t < TR; ++t) part[0] = fmaf(wf[t], sb[t], part[0]);
+      // M_ij = m_j - ln(K_ij) / lambda for the row-scaled K
+      part[0] = fmaf(part[0], kNegLn2 * p.inv_lam, cm);
       sum_low<HALF ? 5 : 6>(part);
       float tot = part[0];
       if constexpr (MW) {
@@ -625,9 +645,8 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         tot = a;
         __syncthreads();
       }
-      tot *= kNegLn2 * p.inv_lam;
       if (il == 0 && (MW ? wave == 0 : true) && active) {
-        p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
+        p.out[k] = vr > 0 ? flag_range(tot) : __int_as_float(0x7FC00000);
         if (p.iters_out) p.iters_out[k] = ran;
       }
     }

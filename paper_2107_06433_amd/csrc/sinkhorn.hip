@@ -88,9 +88,13 @@ __global__ void __launch_bounds__(256) sink_stream_kernel(SinkParams p) {
     if (p.store_u)
       for (int c = threadIdx.x; c < S; c += 256) p.u[(size_t)k * S + c] = su[c];
     if (p.do_final) {
+      // d_k = sum_j c_j (m_j - (ln 2 / lambda) (K_j . (u log2 K_j)) / (K_j . u))
+      // for the row-scaled K (M_ij = m_j - ln(K_ij) / lambda)
+      const float scale = kNegLn2 * p.inv_lam;
       float part = 0.f;
       for (int j = wave; j < n; j += 4) {
-        const float* row = p.kt + (size_t)p.wl[beg + j] * S;
+        const int wj = p.wl[beg + j];
+        const float* row = p.kt + (size_t)wj * S;
         float a = 0.f, b = 0.f;
         for (int c = lane; c < S; c += 64) {
           const float ku = row[c] * su[c];
@@ -100,13 +104,13 @@ __global__ void __launch_bounds__(256) sink_stream_kernel(SinkParams p) {
         a = sum_wave(a);
         b = sum_wave(b);
         const float cj = p.wn[beg + j];
-        if (cj > 0.f) part += cj * fast_div(b, a);
+        if (cj > 0.f) part += cj * fmaf(scale, fast_div(b, a), p.km[wj]);
       }
       if (lane == 0) sred[wave] = part;
       __syncthreads();
       if (threadIdx.x == 0) {
-        const float tot = (((sred[0] + sred[1]) + sred[2]) + sred[3]) * (kNegLn2 * p.inv_lam);
-        p.out[k] = vr > 0 ? tot : __int_as_float(0x7FC00000);
+        const float tot = ((sred[0] + sred[1]) + sred[2]) + sred[3];
+        p.out[k] = vr > 0 ? flag_range(tot) : __int_as_float(0x7FC00000);
         if (p.iters_out) p.iters_out[k] = p.iters;  // no tolerance stop on this path
       }
     }

@@ -48,7 +48,7 @@ struct CorpusLayout {
 // codes sit at offset 0 so that wmd_query_errors() can find them from the
 // workspace pointer alone.
 struct QueryLayout {
-  size_t err, vr, qid, r, cinfo, qn, q32, q16, kt, u, w, total;
+  size_t err, vr, qid, r, cinfo, qinfo, qn, q32, q16, kt, km, u, w, total;
   static QueryLayout make(int B, int64_t C, int64_t U, int dp, int64_t N, int64_t nnz,
                           bool need_u, bool need_w) {
     QueryLayout L{};
@@ -59,10 +59,12 @@ struct QueryLayout {
     L.qid = take(sizeof(int) * (size_t)C);
     L.r = take(sizeof(float) * (size_t)C);
     L.cinfo = take(sizeof(int2) * (size_t)C);
+    L.qinfo = take(sizeof(int2) * (size_t)B);           // per query: first column, width S
     L.qn = take(sizeof(float) * (size_t)C);
     L.q32 = take(sizeof(float) * (size_t)C * dp);
     L.q16 = take(sizeof(uint16_t) * (size_t)C * dp);
     L.kt = take(sizeof(float) * (size_t)C * (size_t)U);
+    L.km = take(sizeof(float) * (size_t)B * (size_t)U);  // per query and row: the row's shift m_j
     L.u = need_u ? take(sizeof(float) * (size_t)C * (size_t)N) : o;
     L.w = need_w ? take(sizeof(float) * (size_t)nnz * (size_t)B) : o;
     L.total = o;
@@ -76,15 +78,25 @@ struct SelectParams {
   const int64_t* q_ptr; const int32_t* q_ids; const float* q_w;
   int B; int64_t V; int d; int dp;
   const float* emb;
-  int* err; int* vr; int* qid; float* r; int2* cinfo; float* qn; float* q32; uint16_t* q16;
+  int* err; int* vr; int* qid; float* r; int2* cinfo; int2* qinfo; float* qn; float* q32; uint16_t* q16;
   int want_bf16;
 };
 
+// The Gibbs kernel is stored row-scaled: row j of query b's block holds
+// exp(-lambda (M_ij - m_j)) with m_j = min_i M_ij over the query's words, and
+// km[b U + j] = m_j.  Scaling a column of K by any positive factor leaves
+// Algorithm 1's u iterates and its distance unchanged (v absorbs the factor),
+// so this is the same computation; every stored row then has maximum 1 and
+// cannot underflow as a whole.  With one query in the call (one_query) the
+// cost-matrix kernel applies the shift itself; otherwise it stores the plain
+// distances (+inf in unused slots) and gibbs_rows_kernel applies it.
 struct CdistParams {
   const float* e32; const uint16_t* e16; const float* en; const int* used; int64_t U;
   const float* q32; const uint16_t* q16; const float* qn; const int* qid; const int2* cinfo;
   int64_t C; int dp; float lam;
   float* kt;
+  float* km;               // B x U row shifts (written here when one_query)
+  int one_query;
   // Fused selection (sel_n > 0): one query of sel_n <= 64 entries and C = its
   // padded width.  Every block selects it and reads the embedding rows of its
   // words itself; block 0 also writes err, vr, r, qid and cinfo (the _out
@@ -99,14 +111,16 @@ struct CdistParams {
 // One fused SDDMM-SpMM launch over the documents of one length bucket for one
 // query.  The same kernel runs every schedule; flags pick the variant.
 struct SinkParams {
-  const float* kt;        // K^T block of the query: U rows x S floats (1 in unused slots)
+  const float* kt;        // K^T block of the query: U rows x S floats (1 in unused slots),
+                          // row j scaled by exp(lambda m_j) (see CdistParams)
+  const float* km;        // U row shifts m_j of the query
   const float* r;         // S slots of the normalised query histogram (0 = unused slot)
   const int* vr;          // device: number of used slots (0 = invalid query)
   const int4* drec;       // documents of the bucket: (first entry lo, hi, length, id)
   const int* wl; const float* wn;
   int ndocs;
   int S;
-  float inv_lam;          // 1 / lambda: the final pass recovers M = -ln(K) / lambda
+  float inv_lam;          // 1 / lambda: the final pass recovers M = m_j - ln(K) / lambda
   float* out;             // row of this query, indexed by document id
   float* u;               // N x S scalings (per-iteration schedules), doc-major
   float* w;               // nnz sparse intermediate (unfused schedule)
@@ -150,8 +164,14 @@ hipError_t launch_prep_emb(const float* emb, int d, int dp, const int* used, int
                            float* e32, uint16_t* e16, float* en, hipStream_t s);
 
 hipError_t launch_select(const SelectParams& p, hipStream_t s);
-// `name` receives the kernel and tile shape that was launched.
-hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name);
+// `name` receives the kernel and tile shape that was launched; `shifted` is set
+// when that kernel stored the row-scaled K itself (one query, skinny kernel),
+// otherwise it stored distances and launch_gibbs_rows must follow.
+hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const char** name, bool* shifted);
+// Row shift of the stored distances of B queries (after a launch_cdist with
+// one_query = 0): m_j = min over each query's used columns, K = exp(-lambda
+// (M - m_j)), unused columns (+inf) become 1.
+hipError_t launch_gibbs_rows(float* kt, float* km, const int2* qinfo, int64_t U, int B, float lam, hipStream_t s);
 // whether launch_cdist can run with the selection fused in (sel_n > 0)
 bool cdist_fuses_select(const CdistParams& p, bool bf16);
 hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s);

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import warnings
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -319,7 +320,10 @@ class Corpus:
         """Distances of every query to every document: float32 [B, N] on the device.
 
         With ``check`` the call waits for the stream and raises ValueError if a
-        query held an invalid id or weight (its row is NaN either way).
+        query held an invalid id or weight (its row is NaN either way); it also
+        counts the distances that came back +Inf (float32 K underflowed for a
+        whole row of a document at this lambda) into ``last_out_of_range`` and
+        warns when there are any.
 
         With ``graph`` the launch sequence is captured into a HIP graph the
         first time and replayed by later calls whose arguments are identical
@@ -350,6 +354,10 @@ class Corpus:
             bad = [(b, QUERY_ERRORS.get(int(c), int(c))) for b, c in enumerate(codes) if c]
             if bad:
                 raise ValueError(f"invalid queries: {bad[:8]}")
+            self.last_out_of_range = int(torch.isposinf(out).sum().item())
+            if self.last_out_of_range:
+                warnings.warn(f"{self.last_out_of_range} distances are +Inf: float32 K = exp(-lambda M) "
+                              f"underflowed for a whole row at lambda={lam:g}", RuntimeWarning, stacklevel=2)
         return out
 
     def set_timing(self, enable: bool):
