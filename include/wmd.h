@@ -189,6 +189,23 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
 wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* wmd_query without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The query workspace is a static device array of
+ * wmd_query_static_capacity() bytes (64 MiB), one copy per GPU, held until the
+ * process ends; this call allocates nothing and calls no allocating routine.
+ * Inputs and `out` are the caller's, as for wmd_query; the distances are the
+ * same bit for bit.  A call whose workspace would exceed the array
+ * (wmd_query_workspace_bytes) returns WMD_ERR_NOT_SUPPORTED, as do the graph
+ * flag and per-kernel timing (both would allocate).  Every call on one GPU
+ * uses the same array: calls that may overlap on the device (other streams,
+ * other threads, other corpora) race and must be ordered by the caller.
+ * Nothing in the array needs to start at zero (every launch writes what it
+ * reads first).  Device error codes stay in the array; a row of an invalid
+ * query is NaN as with wmd_query. */
+size_t wmd_query_static_capacity(void);
+wmd_status wmd_query_static(wmd_corpus* c, const wmd_query_desc* q, float* out, void* stream);
+
 /* Per-query device error codes of the last wmd_query on `workspace`
  * (0 = ok, 1 = id out of range, 2 = bad weight, 3 = no positive weight).
  * Copies B int32 into host `codes` and synchronises `stream`. */

@@ -47,8 +47,41 @@ bool mul_ok(size_t a, size_t b, size_t* out) {
 
 }  // namespace
 
+// Query workspace of wmd_query_static (see wmd.h): a device array of fixed
+// size.  Every GPU the library runs on holds its own copy until the process
+// ends.  Host code never uses this name as an address: scratch_address()
+// resolves the copy of the current device with hipGetSymbolAddress, and that
+// pointer is what the kernels receive.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the scratch array on device `dev`, which must be current;
+// resolved once per device.
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 struct wmd_corpus {
   int device = 0;
+  void* scratch = nullptr;  // this device's copy of the static query scratch
   int64_t V = 0, N = 0, nnz = 0, U = 0;
   int d = 0, dp = 0;
   const float* emb = nullptr;
@@ -176,6 +209,7 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
   std::unique_ptr<wmd_corpus> c(new (std::nothrow) wmd_corpus());
   if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "out of host memory");
   WMD_HIP(hipGetDevice(&c->device));
+  WMD_HIP(scratch_address(c->device, &c->scratch));
   for (int i = 0; i < wmd_corpus::kSide; ++i) {
     WMD_HIP(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
     WMD_HIP(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
@@ -743,6 +777,30 @@ wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_s
   if (!sink_config_fits(cfg, S, cap)) return fail(WMD_ERR_INVALID_ARGUMENT, "shape cannot run this (S, cap)");
   c->pinned[{S, cap}] = cfg;
   return WMD_OK;
+}
+
+size_t wmd_query_static_capacity(void) { return kScratchBytes; }
+
+wmd_status wmd_query_static(wmd_corpus* c, const wmd_query_desc* q, float* out, void* stream) {
+  g_err.clear();
+  if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
+  if (q->flags & WMD_QUERY_GRAPH)
+    return fail(WMD_ERR_NOT_SUPPORTED, "wmd_query_static does not capture graphs (instantiating one allocates)");
+  if (c->timing)
+    return fail(WMD_ERR_NOT_SUPPORTED, "wmd_query_static does not run while per-kernel timing is enabled");
+  if (!c->scratch) return fail(WMD_ERR_DEVICE, "static scratch of the corpus device is not resolved");
+  QueryPlan plan;
+  wmd_status st = plan_query(c, q->B, q->q_ptr_host, &plan);
+  if (st != WMD_OK) return st;
+  if (q->schedule < WMD_SCHEDULE_AUTO || q->schedule > WMD_SCHEDULE_UNFUSED)
+    return fail(WMD_ERR_INVALID_ARGUMENT, "unknown schedule");
+  const int schedule = q->schedule == WMD_SCHEDULE_AUTO ? WMD_SCHEDULE_RESIDENT : q->schedule;
+  const size_t need = layout_for(c, plan, schedule).total;
+  if (need > kScratchBytes)
+    return fail(WMD_ERR_NOT_SUPPORTED, "this call needs " + std::to_string(need) +
+                                           " bytes of query workspace; the static scratch holds " +
+                                           std::to_string(kScratchBytes) + " (use wmd_query with a workspace)");
+  return enqueue_query(c, q, out, c->scratch, kScratchBytes, stream, false);
 }
 
 wmd_status wmd_query_errors(const void* workspace, int32_t B, int32_t* codes, void* stream) {

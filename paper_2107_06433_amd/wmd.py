@@ -33,6 +33,7 @@ EXPORTS = [
     "wmd_corpus_workspace_bytes", "wmd_create_corpus", "wmd_get_corpus_info", "wmd_destroy",
     "wmd_query_workspace_bytes", "wmd_query", "wmd_query_errors", "wmd_set_timing", "wmd_get_timing",
     "wmd_get_launches", "wmd_sink_candidates", "wmd_set_sink_shape", "wmd_set_merge", "wmd_last_error",
+    "wmd_query_static", "wmd_query_static_capacity",
 ]
 MERGE = {"all": 0, "none": 1}
 TUNING_FILE = os.path.join(_PKG, "tuning", "gfx950_sink_shapes.json")
@@ -104,6 +105,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wmd_query_workspace_bytes.restype = sz
     lib.wmd_query.argtypes = [vp, ctypes.POINTER(QueryDesc), vp, vp, sz, vp]
     lib.wmd_query.restype = i32
+    lib.wmd_query_static.argtypes = [vp, ctypes.POINTER(QueryDesc), vp, vp]
+    lib.wmd_query_static.restype = i32
+    lib.wmd_query_static_capacity.argtypes = []
+    lib.wmd_query_static_capacity.restype = sz
     lib.wmd_query_errors.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), vp]
     lib.wmd_query_errors.restype = i32
     lib.wmd_set_timing.argtypes = [vp, i32]
@@ -358,6 +363,24 @@ class Corpus:
             if self.last_out_of_range:
                 warnings.warn(f"{self.last_out_of_range} distances are +Inf: float32 K = exp(-lambda M) "
                               f"underflowed for a whole row at lambda={lam:g}", RuntimeWarning, stacklevel=2)
+        return out
+
+    def query_static(self, batch: QueryBatch, lam: float, max_iter: int, out: torch.Tensor,
+                     cdist: str = "fp32", schedule: str = "auto", stream=None, tol: float = 0.0,
+                     iters: torch.Tensor | None = None) -> torch.Tensor:
+        """wmd_query_static: the same distances into the caller's ``out`` (float32
+        [B, N] on the device) with the library's static device scratch as the
+        query workspace -- no device allocation by this call."""
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() < batch.B * self.N:
+            raise ValueError("out must be a device float32 tensor of B*N elements")
+        if iters is not None and (iters.dtype != torch.int32 or iters.numel() < batch.B * self.N or not iters.is_cuda):
+            raise ValueError("iters must be a device int32 tensor of B*N elements")
+        desc = QueryDesc(B=batch.B, q_ptr_host=batch.q_ptr_host.ctypes.data, q_ptr=_ptr(batch.q_ptr),
+                         q_ids=_ptr(batch.ids), q_weights=_ptr(batch.weights), lam=float(lam),
+                         max_iter=int(max_iter), cdist=CDIST[cdist], schedule=SCHEDULE[schedule],
+                         tol=float(tol), iters=_ptr(iters), flags=0)
+        with torch.cuda.device(self.device):
+            _check(lib().wmd_query_static(self._h, ctypes.byref(desc), _ptr(out), _stream_handle(stream)))
         return out
 
     def set_timing(self, enable: bool):
