@@ -9,6 +9,14 @@ max_iter fused SDDMM-SpMM iterations and the final pass) for the workload's
 query batch against its resident corpus; inputs are in device memory before
 the timed region starts.  The value is target-docs x iterations per second.
 With --plain the batched workload's queries are issued one call each.
+
+The default run (workload single) also reports, under "legs", the metric's
+other parts at full size: the batched workload in one call (bf16 and fp32
+cost matrix) against the same 64 queries issued one plain fp32 call each, with
+their ratio; a short open-loop serving trace (p50/p99 latency at 2,000
+queries/s and the highest stable rate tried); and the measured ceilings of
+the GPU (HBM stream, K^T row gather, VALU rates) that the roofline fractions
+are also given against.  --no-legs skips them.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -28,7 +36,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "target-docs·iters/s for Sinkhorn WMD (plain vs batched); p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"alu": 157.3, "mfma_fp32": 157.3, "mfma_bf16": 2500.0}
+# FP32 VALU: every HIP source is built with packed FP32 instructions disabled,
+# so an FMA is one wave64 instruction per 4 cycles per SIMD: 256 CU x 4 SIMD x
+# 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s (the published 157.3 counts packed
+# FP32, reported beside it).  Matrix-core peaks as published.
+PEAK_TFLOPS = {"alu": 78.6, "alu_packed_published": 157.3, "mfma_fp32": 157.3, "mfma_bf16": 2500.0}
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
@@ -54,8 +66,12 @@ def parse():
     ap.add_argument("--sweep", type=float, nargs="*", default=[], help="serving: extra arrival rates to try")
     ap.add_argument("--mem-budget-gb", type=float, default=24.0, help="serving: device memory for queries")
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--per-query-launches", action="store_true",
+                    help="every query gets its own Sinkhorn launches (no launches shared between queries)")
     ap.add_argument("--graph", action="store_true",
                     help="capture each call's launches into a HIP graph once and replay it (on a side stream)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="single workload: skip the batched, serving and ceiling legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for HBM counters)")
     return ap.parse_args()
@@ -177,7 +193,8 @@ def serving(args):
     tfl = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": tfl, "peak": PEAK_TFLOPS["alu"], "unit": "TFLOP/s",
             "frac": tfl / PEAK_TFLOPS["alu"], "kernel": dom["name"], "avg_launch_us": avg_ms * 1e3,
-            "traffic": None}
+            "peak_basis": "FP32 FMA without packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz",
+            "frac_of_published_packed_peak": tfl / PEAK_TFLOPS["alu_packed_published"], "traffic": None}
     res = {
         "metric": METRIC, "value": main_st["docs_iters_per_s"], "unit": "docs*iters/s", "n_gpus": 1,
         "steps": main_st["completed"], "warmup": args.serve_warmup,
@@ -200,6 +217,106 @@ def serving(args):
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res))
+
+
+def _ms_per_step(fn, warmup: int, steps: int) -> float:
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def batched_leg() -> dict:
+    """The batched workload at full size: one call for all 64 queries (bf16
+    and fp32 cost matrix) and the same queries issued one plain fp32 call
+    each (also with the paper's one-launch-per-iteration schedule, as
+    context); docs*iters/s and the batched/plain ratios."""
+    import torch
+
+    from paper_2107_06433_amd import synth, wmd
+    w = synth.make_workload("batched")
+    c, Q = w.corpus, w.queries
+    corpus = wmd.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, c.weights)
+    dev = corpus.device
+    batch = wmd.QueryBatch.from_arrays(Q.q_ptr, Q.ids, Q.weights)
+    singles = [wmd.QueryBatch.from_arrays([0, len(Q.query(b)[0])], *Q.query(b)) for b in range(Q.B)]
+    out = torch.empty((Q.B, c.N), dtype=torch.float32, device=dev)
+    ws = torch.empty(corpus.workspace_bytes(batch), dtype=torch.uint8, device=dev)
+    sws = {sch: torch.empty(max(corpus.workspace_bytes(b, sch) for b in singles), dtype=torch.uint8, device=dev)
+           for sch in ("auto", "per_iteration")}
+    docs_iters = Q.B * c.N * w.max_iter
+
+    def one_call(cd):
+        return lambda: corpus.query(batch, w.lam, w.max_iter, cdist=cd, out=out, workspace=ws, check=False)
+
+    def per_query(sch):
+        def run():
+            for b, sb in enumerate(singles):
+                corpus.query(sb, w.lam, w.max_iter, cdist="fp32", schedule=sch, out=out[b:b + 1],
+                             workspace=sws[sch], check=False)
+        return run
+
+    res = {"config": describe(w, False)}
+    for key, fn, warm, steps in (("batched_bf16", one_call("bf16"), 1, 4), ("batched_fp32", one_call("fp32"), 1, 4),
+                                 ("plain_fp32", per_query("auto"), 1, 3),
+                                 ("plain_fp32_per_iteration_schedule", per_query("per_iteration"), 1, 1)):
+        ms = _ms_per_step(fn, warm, steps)
+        res[key] = {"ms_per_step": ms, "value": docs_iters / (ms * 1e-3), "steps": steps}
+        print(f"[bench] batched leg {key}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    res["ratio_batched_bf16_vs_plain_fp32"] = res["batched_bf16"]["value"] / res["plain_fp32"]["value"]
+    res["ratio_batched_bf16_vs_plain_fp32_per_iteration"] = (
+        res["batched_bf16"]["value"] / res["plain_fp32_per_iteration_schedule"]["value"])
+    res["unit"] = "docs*iters/s"
+    res["note"] = ("plain = the same 64 queries, one wmd_query(B=1) each, resident fused kernel (the library's "
+                   "own per-query path); plain_fp32_per_iteration_schedule = one fused SDDMM-SpMM launch per "
+                   "iteration per query, the paper's loop structure (context only)")
+    del corpus
+    torch.cuda.empty_cache()
+    return res
+
+
+def serving_leg(rates=(2000.0, 1500.0, 1000.0), measured=4000, warm=500) -> dict:
+    """A short open-loop serving trace on the full serving corpus (Poisson
+    arrivals, continuous batching on three streams, bf16 cost matrix): p50/p99
+    at 2,000 queries/s and at lower rates; the highest rate served within 3%."""
+    import torch
+
+    from paper_2107_06433_amd import serve, synth, wmd
+    n = warm + measured
+    w = synth.make_workload("serving", n_queries=n)
+    c, Q = w.corpus, w.queries
+    corpus = wmd.Corpus.from_numpy(c.emb, c.doc_ptr, c.word_ids, c.weights)
+    reqs_of = lambda k: [serve.Request(ids=Q.query(b)[0], weights=Q.query(b)[1], arrival=0.0) for b in range(k)]
+
+    def trace(rate, k, wk):
+        ex = serve.GpuExecutor(corpus, w.lam, w.max_iter, cdist="bf16", streams=3)
+        sch = serve.Scheduler(ex, 24 << 30, 64, max_inflight=3)
+        arr = w.arrivals[:k] * (2000.0 / rate)
+        st = serve.run_trace(sch, reqs_of(k), arr - arr[0], warmup=wk)
+        torch.cuda.synchronize()
+        st["rate"] = rate
+        st["docs_iters_per_s"] = st["served_qps"] * c.N * w.max_iter
+        print(f"[bench] serving leg {rate:g} q/s: served {st['served_qps']:.0f} q/s, p50 {st['p50_ms']:.1f} ms, "
+              f"p99 {st['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        return {k2: st[k2] for k2 in ("rate", "offered_qps", "served_qps", "p50_ms", "p99_ms", "mean_ms",
+                                      "completed", "batches", "docs_iters_per_s")}
+
+    trace(rates[0], 300, 0)  # warm the allocator and the launch plans
+    runs = [trace(rates[0], n, warm)] + [trace(r, min(n, 2500), 300) for r in rates[1:]]
+    stable = [r["rate"] for r in runs if r["served_qps"] >= 0.97 * r["rate"]]
+    res = {"config": (f"serving: V={c.V} d={c.d} N={c.N} docs of 20-60 Zipf(1.1) words (nnz={c.nnz}), v_r lognormal "
+                      f"median 25 sigma 1 cap 500, Poisson arrivals, bf16 cost matrix, lambda={w.lam:g}, "
+                      f"{w.max_iter} iterations, {measured} measured queries after {warm}"),
+           "at_2000_qps": runs[0], "sweep": runs[1:], "highest_stable_rate_tried": max(stable, default=None),
+           "unit": "docs*iters/s"}
+    del corpus
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -250,7 +367,7 @@ def main():
         for bt, o, ws, its in zip(batches, outs, wss, itss):
             corpus.query(bt, w.lam, w.max_iter, cdist=args.cdist, schedule=args.schedule, out=o,
                          workspace=ws, check=False, tol=args.tol, iters=its, stream=run_stream,
-                         graph=args.graph)
+                         graph=args.graph, per_query_launches=args.per_query_launches)
 
     # validity check of the configuration before timing
     step()
@@ -301,7 +418,9 @@ def main():
             roof = {"bound": "mfma", "achieved": tfl, "peak": peak_t, "unit": "TFLOP/s"}
     elif args.schedule in ("auto", "resident"):
         tfl = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": tfl, "peak": PEAK_TFLOPS["alu"], "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "achieved": tfl, "peak": PEAK_TFLOPS["alu"], "unit": "TFLOP/s",
+                "peak_basis": "FP32 FMA without packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz",
+                "frac_of_published_packed_peak": tfl / PEAK_TFLOPS["alu_packed_published"]}
     else:
         gbs = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
@@ -319,6 +438,40 @@ def main():
     except (OSError, ValueError):
         pass
 
+    if args.workload == "single" and not args.no_legs:
+        from paper_2107_06433_amd import microbench
+        ids_c, U_c = microbench.corpus_ids(c.word_ids)
+        S_c = int((int(np.diff(Q.q_ptr).max()) + 3) // 4 * 4)
+        ceil = microbench.measure(torch.from_numpy(ids_c).to(dev), U_c, S_c)
+        print(f"[bench] ceilings: {json.dumps(ceil)}", file=sys.stderr, flush=True)
+        if roof["unit"] == "TFLOP/s" and roof["bound"] == "alu":
+            roof["measured_peak"] = ceil["valu"]["fma_TFLOPs"]
+            roof["measured_peak_source"] = "wmd_bench_valu float32 FMA chains (this run)"
+            # the paper's bandwidth model next to the ALU one: the launch's
+            # HBM stream (entries, records) and its K^T row gather at the
+            # measured ceilings, its flops at the measured FMA rate
+            nnz = float(c.nnz)
+            vr = float(np.diff(Q.q_ptr).sum())
+            t_stream = (8.0 * nnz + 20.0 * c.N) / (ceil["hbm"]["read_GBps"] * 1e9)
+            t_gather = 4.0 * vr * nnz / (ceil["gather"]["GBps"] * 1e9)
+            t_alu = dom["flops"] / dom["launches"] / (ceil["valu"]["fma_TFLOPs"] * 1e12)
+            roof["model_fraction"] = max(t_stream, t_gather, t_alu) / (avg_ms * 1e-3)
+            roof["model_terms_us"] = {"hbm_stream": t_stream * 1e6, "row_gather": t_gather * 1e6,
+                                      "fma": t_alu * 1e6}
+        elif roof["unit"] == "GB/s":
+            roof["measured_peak"] = ceil["hbm"]["read_GBps"]
+            roof["measured_peak_source"] = "wmd_bench_stream read (this run)"
+        if "measured_peak" in roof:
+            roof["frac_of_measured"] = roof["achieved"] / roof["measured_peak"]
+        legs = {"ceilings": ceil}
+        legs["batched"] = batched_leg()
+        legs["serving"] = serving_leg()
+    else:
+        legs = None
+    if roof.get("traffic") is not None:
+        roof["traffic_source"] = ("profiles/pmc_traffic.json: rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel "
+                                  "and source hash, scaled by a plain copy (not measured in this run)")
+
     res = {
         "metric": METRIC, "value": value, "unit": "docs*iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -335,6 +488,8 @@ def main():
         "source_hash": source_hash(),
         "device": torch.cuda.get_device_name(0),
     }
+    if legs is not None:
+        res["legs"] = legs
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

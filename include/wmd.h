@@ -163,6 +163,12 @@ typedef struct {
  * ignored while per-kernel timing is enabled.  A corpus keeps its 128 most
  * recently used graphs. */
 #define WMD_QUERY_GRAPH 1
+/* flags: give every query its own Sinkhorn launches.  By default (resident
+ * schedule) the queries of a call whose launch plans are identical -- the
+ * same kernel shape, length buckets and row bodies, which depend on the query
+ * width only through the shape -- share one launch of up to 64 queries.  The
+ * results are the same bit for bit either way. */
+#define WMD_QUERY_PER_QUERY_LAUNCHES 2
 
 /* Bytes of query workspace for B queries with these offsets and schedule
  * (0 on invalid input).  Dominated by K^T: 4 * U * sum_b S_b bytes, S_b =

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwmd.so")
-SOURCES = ["prep.hip", "cdist.hip", "sinkhorn.hip", "capi.cpp"] + [f"sink_cg{i}.hip" for i in range(7)]
+SOURCES = ["prep.hip", "cdist.hip", "sinkhorn.hip", "capi.cpp", "microbench.hip"] + [f"sink_cg{i}.hip" for i in range(7)]
 
 
 def hipcc() -> str:

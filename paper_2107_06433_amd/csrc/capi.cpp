@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <list>
 #include <map>
 #include <cmath>
@@ -79,6 +80,21 @@ hipError_t scratch_address(int dev, void** out) {
 
 }  // namespace
 
+// One Sinkhorn launch of a query's plan: the length buckets that one-wave
+// items hold merged into one launch, or one bucket with a shape of its own.
+// Plans depend on the padded query width S only through the kernel shape, so
+// queries whose units have equal keys share one launch (SinkQuerySet).
+struct SinkUnit {
+  bool merged = false;
+  MergePlan plan;                 // merged: shape, member buckets (longest first), row bodies
+  int nb = 0;                     // buckets in the unit
+  int bk[kMergeMax] = {};         // their indices, in launch order
+  SinkConfig cfg{};               // one bucket: its shape
+  double nzb = 0.0, ndd = 0.0;    // entries and documents the unit covers
+  std::string name;
+  std::vector<int64_t> key;
+};
+
 struct wmd_corpus {
   int device = 0;
   void* scratch = nullptr;  // this device's copy of the static query scratch
@@ -94,32 +110,48 @@ struct wmd_corpus {
   int64_t bucket_nnz[kNumBuckets] = {};  // entries of the documents in each bucket
   int* docs() const { return at<int>(ws, L.docs); }
 
-  // per-launch timing (wmd_set_timing)
+  // per-launch timing (wmd_set_timing); timing_mu serialises timed calls
   struct Rec { std::string name; size_t ev; double flops, bytes; int query, S, cap, ndocs; };
-  bool timing = false;
+  std::atomic<bool> timing{false};
   std::vector<hipEvent_t> events;  // pool, reused; pairs (start, end)
   std::vector<Rec> recs;
+  std::mutex timing_mu;
 
-  // side streams (default priority) that run the independent Sinkhorn launch
-  // groups of a call concurrently, forked from and joined back into the
-  // caller's stream with events
+  // Side streams (default priority) that run the independent Sinkhorn
+  // launches of a call concurrently, forked from and joined back into the
+  // caller's stream with events.  Each caller stream gets a set of its own,
+  // so calls on different streams never queue behind each other here; a call
+  // holds its set's lock while it enqueues (through the end of a capture).
   static constexpr int kSide = 4;
-  hipStream_t side[kSide] = {};
-  hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[kSide] = {};
-  std::mutex side_mu;  // one call at a time enqueues on the side streams
+  struct SideSet {
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kSide] = {};
+    std::mutex mu;
+    ~SideSet() {
+      for (int i = 0; i < kSide; ++i) {
+        if (side[i]) (void)hipStreamDestroy(side[i]);
+        if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+      }
+      if (fork_ev) (void)hipEventDestroy(fork_ev);
+    }
+  };
+  static constexpr size_t kMaxSideSets = 16;  // further caller streams run without forking
+  std::map<hipStream_t, std::unique_ptr<SideSet>> sides;
+  std::mutex sides_mu;
 
   // captured launch sequences (WMD_QUERY_GRAPH), most recent first
   struct GraphEntry { std::vector<uint64_t> key; hipGraph_t graph; hipGraphExec_t exec; };
   std::list<GraphEntry> graphs;
-  int merge = WMD_MERGE_ALL;
   std::mutex graph_mu;
   static constexpr size_t kMaxGraphs = 128;
 
-  // Sinkhorn shapes pinned per (padded query width, bucket capacity)
+  // launch planning: merge mode, Sinkhorn shapes pinned per (padded query
+  // width, bucket capacity), and the per-width plans derived from them
+  std::mutex cfg_mu;
+  int merge = WMD_MERGE_ALL;
   std::map<std::pair<int, int>, SinkConfig> pinned;
-  // tag of the next timed launch (query, S, cap, ndocs)
-  int tag_query = -1, tag_S = 0, tag_cap = 0, tag_ndocs = 0;
+  std::map<int, std::shared_ptr<const std::vector<SinkUnit>>> plans;
 
   ~wmd_corpus() {
     for (auto& g : graphs) {
@@ -127,11 +159,6 @@ struct wmd_corpus {
       (void)hipGraphDestroy(g.graph);
     }
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    for (int i = 0; i < kSide; ++i) {
-      if (side[i]) (void)hipStreamDestroy(side[i]);
-      if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
-    }
-    if (fork_ev) (void)hipEventDestroy(fork_ev);
   }
 };
 
@@ -139,11 +166,16 @@ namespace {
 
 constexpr size_t kMaxTimedLaunches = 1000000;
 
-// Launches `fn` on stream s; with timing on, brackets it with two events and
-// records its algorithmic work.
+// Launch tag of a timing record: query (the first one of a multi-query
+// launch), padded width S, bucket capacity (0: several buckets) and documents.
+struct Tag { int query = -1, S = 0, cap = 0, ndocs = 0; };
+
+// Launches `fn` on stream s; in a timed call (the caller holds timing_mu),
+// brackets it with two events and records its algorithmic work.
 template <class F>
-hipError_t timed_launch(wmd_corpus* c, hipStream_t s, const std::string& name, double flops, double bytes, F&& fn) {
-  if (!c->timing || c->recs.size() >= kMaxTimedLaunches) return fn();
+hipError_t timed_launch(wmd_corpus* c, bool timed, hipStream_t s, const std::string& name, double flops,
+                        double bytes, const Tag& tag, F&& fn) {
+  if (!timed || c->recs.size() >= kMaxTimedLaunches) return fn();
   const size_t ev = 2 * c->recs.size();
   while (c->events.size() < ev + 2) {
     hipEvent_t e;
@@ -157,8 +189,31 @@ hipError_t timed_launch(wmd_corpus* c, hipStream_t s, const std::string& name, d
   if (err != hipSuccess) return err;
   err = hipEventRecord(c->events[ev + 1], s);
   if (err != hipSuccess) return err;
-  c->recs.push_back({name, ev, flops, bytes, c->tag_query, c->tag_S, c->tag_cap, c->tag_ndocs});
+  c->recs.push_back({name, ev, flops, bytes, tag.query, tag.S, tag.cap, tag.ndocs});
   return hipSuccess;
+}
+
+// The side-stream set of caller stream s (created on first use), or null
+// when the corpus already serves its maximum number of caller streams.
+wmd_status side_set(wmd_corpus* c, hipStream_t s, wmd_corpus::SideSet** out) {
+  *out = nullptr;
+  std::lock_guard<std::mutex> lock(c->sides_mu);
+  auto it = c->sides.find(s);
+  if (it != c->sides.end()) {
+    *out = it->second.get();
+    return WMD_OK;
+  }
+  if (c->sides.size() >= wmd_corpus::kMaxSideSets) return WMD_OK;
+  std::unique_ptr<wmd_corpus::SideSet> set(new (std::nothrow) wmd_corpus::SideSet());
+  if (!set) return fail(WMD_ERR_INVALID_ARGUMENT, "out of host memory");
+  for (int i = 0; i < wmd_corpus::kSide; ++i) {
+    WMD_HIP(hipStreamCreateWithFlags(&set->side[i], hipStreamNonBlocking));
+    WMD_HIP(hipEventCreateWithFlags(&set->join_ev[i], hipEventDisableTiming));
+  }
+  WMD_HIP(hipEventCreateWithFlags(&set->fork_ev, hipEventDisableTiming));
+  *out = set.get();
+  c->sides.emplace(s, std::move(set));
+  return WMD_OK;
 }
 
 }  // namespace
@@ -210,11 +265,6 @@ wmd_status wmd_create_corpus(const wmd_corpus_desc* desc, void* stream, wmd_corp
   if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "out of host memory");
   WMD_HIP(hipGetDevice(&c->device));
   WMD_HIP(scratch_address(c->device, &c->scratch));
-  for (int i = 0; i < wmd_corpus::kSide; ++i) {
-    WMD_HIP(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
-    WMD_HIP(hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
-  }
-  WMD_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
   c->V = D.V; c->N = D.N; c->nnz = D.nnz; c->d = D.d; c->dp = padded_dim(D.d);
   c->emb = D.emb; c->doc_ptr = D.doc_ptr;
   c->L = CorpusLayout::make(D.V, D.d, D.N, D.nnz);
@@ -357,8 +407,79 @@ size_t wmd_query_workspace_bytes(const wmd_corpus* c, int32_t B, const int64_t* 
   return layout_for(c, plan, schedule).total;
 }
 
-static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,
-                                size_t workspace_bytes, void* stream, bool in_graph) {
+// The Sinkhorn launch units of a query of padded width S, built once per
+// width and kept until the merge mode or a pinned shape changes.  Per query,
+// the length buckets that one-wave items hold share one launch; the others
+// (and any bucket with a pinned shape) get launches of their own.
+static wmd_status units_for(wmd_corpus* c, int S, std::shared_ptr<const std::vector<SinkUnit>>* out) {
+  std::lock_guard<std::mutex> lock(c->cfg_mu);
+  auto hit = c->plans.find(S);
+  if (hit != c->plans.end()) {
+    *out = hit->second;
+    return WMD_OK;
+  }
+  auto units = std::make_shared<std::vector<SinkUnit>>();
+  int caps[kNumBuckets], nds[kNumBuckets], bks[kNumBuckets], nm = 0;
+  for (int bk = 0; bk < kNumBuckets; ++bk) {
+    const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
+    if (nd == 0) continue;
+    caps[nm] = kBucketCap[bk]; nds[nm] = (int)nd; bks[nm] = bk; ++nm;
+  }
+  bool in_merge[kNumBuckets] = {};
+  MergePlan mp;
+  if (c->merge == WMD_MERGE_ALL && nm > 1 && plan_merge(S, caps, nds, nm, &mp) && mp.n > 1) {
+    SinkUnit u;
+    u.merged = true;
+    u.plan = mp;
+    u.nb = mp.n;
+    u.key = {1, mp.tc, mp.trmax, mp.lg_cg, mp.n};
+    for (int g = 0; g < mp.n; ++g) {
+      const int bk = bks[mp.member[g]];
+      in_merge[bk] = true;
+      u.bk[g] = bk;
+      u.nzb += (double)c->bucket_nnz[bk];
+      u.ndd += (double)nds[mp.member[g]];
+      u.key.push_back(bk);
+      u.key.push_back(mp.body[g]);
+    }
+    u.name = "sink_merge_kernel<" + std::to_string(mp.tc) + "," + std::to_string(mp.trmax) + "," +
+             std::to_string(mp.lg_cg) + ">x" + std::to_string(mp.n);
+    units->push_back(std::move(u));
+  }
+  for (int bk = 0; bk < kNumBuckets; ++bk) {
+    const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
+    if (nd == 0 || in_merge[bk]) continue;
+    SinkUnit u;
+    u.nb = 1;
+    u.bk[0] = bk;
+    auto pin = c->pinned.find({S, kBucketCap[bk]});
+    if (pin != c->pinned.end()) {
+      u.cfg = pin->second;
+    } else if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &u.cfg)) {
+      return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
+                                             " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
+    }
+    u.nzb = (double)c->bucket_nnz[bk];
+    u.ndd = (double)nd;
+    const SinkConfig& cfg = u.cfg;
+    u.key = {0, bk, cfg.tc, cfg.tr, cfg.lg_cg, cfg.nwaves, cfg.maxw, cfg.stream ? 1 : 0};
+    u.name = cfg.stream ? std::string("sink_stream_kernel")
+                        : cfg.multiwave ? "sink_kernel<" + std::to_string(cfg.tc) + "," + std::to_string(cfg.tr) +
+                                              "," + std::to_string(cfg.lg_cg) + "," + std::to_string(cfg.maxw) +
+                                              ">x" + std::to_string(cfg.nwaves)
+                                        : "sink_merge_kernel<" + std::to_string(cfg.tc) + "," +
+                                              std::to_string(cfg.tr) + "," + std::to_string(cfg.lg_cg) + ">x1";
+    units->push_back(std::move(u));
+  }
+  c->plans.emplace(S, units);
+  *out = units;
+  return WMD_OK;
+}
+
+// Descriptor checks that need nothing from the corpus object (which is not
+// dereferenced before they pass).
+static wmd_status check_query_desc(const wmd_corpus* c, const wmd_query_desc* q, const float* out,
+                                   const void* workspace) {
   if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
   if (!out || !workspace) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL output or workspace");
   if (!q->q_ptr || !q->q_ids || !q->q_weights) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL device query pointer");
@@ -369,8 +490,19 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
   if (!(q->tol >= 0.f) || !std::isfinite(q->tol)) return fail(WMD_ERR_INVALID_ARGUMENT, "tol must be finite and >= 0");
   if (q->tol > 0.f && q->schedule != WMD_SCHEDULE_AUTO && q->schedule != WMD_SCHEDULE_RESIDENT)
     return fail(WMD_ERR_NOT_SUPPORTED, "a tolerance stop needs the resident schedule");
+  return WMD_OK;
+}
+
+// Enqueues the whole path of one call.  `side`: the caller stream's side set,
+// locked by the caller, or null to keep every launch on the caller's stream.
+// `timed`: record per-launch events (the caller holds timing_mu).
+static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace,
+                                size_t workspace_bytes, void* stream, bool in_graph, wmd_corpus::SideSet* side,
+                                bool timed) {
+  wmd_status st = check_query_desc(c, q, out, workspace);
+  if (st != WMD_OK) return st;
   QueryPlan plan;
-  wmd_status st = plan_query(c, q->B, q->q_ptr_host, &plan);
+  st = plan_query(c, q->B, q->q_ptr_host, &plan);
   if (st != WMD_OK) return st;
   const int schedule = q->schedule == WMD_SCHEDULE_AUTO ? WMD_SCHEDULE_RESIDENT : q->schedule;
   const QueryLayout L = layout_for(c, plan, schedule);
@@ -380,10 +512,17 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
   int dev = 0;
   WMD_HIP(hipGetDevice(&dev));
   if (dev != c->device) return fail(WMD_ERR_INVALID_ARGUMENT, "current device differs from the corpus device");
+  // launch units of every query (by padded width)
+  std::vector<std::shared_ptr<const std::vector<SinkUnit>>> qunits((size_t)q->B);
+  for (int b = 0; b < q->B; ++b) {
+    st = units_for(c, (int)plan.S[(size_t)b], &qunits[(size_t)b]);
+    if (st != WMD_OK) return st;
+  }
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = workspace;
   const CorpusLayout& CL = c->L;
+  const Tag none{};
 
   // a1: query selection and slot layout
   SelectParams sp{};
@@ -394,7 +533,6 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
   sp.qn = at<float>(ws, L.qn);
   sp.q32 = at<float>(ws, L.q32); sp.q16 = at<uint16_t>(ws, L.q16);
   sp.want_bf16 = q->cdist == WMD_CDIST_BF16;
-  c->tag_query = -1; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = 0;
   const double T = (double)q->q_ptr_host[q->B];  // raw query entries = sum of v_r
   const double esz = q->cdist == WMD_CDIST_BF16 ? 2.0 : 4.0;
   const double sel_bytes = T * 8.0 + T * c->d * 4.0 + (double)plan.C * c->dp * (4.0 + esz);
@@ -419,7 +557,7 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
     cp.q_ids = q->q_ids; cp.q_w = q->q_weights; cp.V = c->V; cp.d = c->d; cp.emb = c->emb;
     cp.err = sp.err; cp.vr = sp.vr; cp.r = sp.r; cp.qid_out = sp.qid; cp.cinfo_out = sp.cinfo;
   } else {
-    WMD_HIP(timed_launch(c, s, "select_kernel", 0.0, sel_bytes, [&] { return launch_select(sp, s); }));
+    WMD_HIP(timed_launch(c, timed, s, "select_kernel", 0.0, sel_bytes, none, [&] { return launch_select(sp, s); }));
   }
   if (c->U > 0) {
     // algorithmic work: 2 U d flops per query word; read the U x d vocabulary
@@ -430,15 +568,16 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
                          (fuse ? sel_bytes : 0.0);
     // the tile shape is picked inside the launch; its name is filled in afterwards
     const char* name = "cdist_kernel";
-    const size_t nrec = c->recs.size();
+    const size_t nrec = timed ? c->recs.size() : 0;
     bool shifted = false;
-    WMD_HIP(timed_launch(c, s, "", flops, bytes, [&] { return launch_cdist(cp, bf16, s, &name, &shifted); }));
-    if (c->recs.size() > nrec) c->recs.back().name = std::string(name) + (fuse ? "+select" : "");
+    WMD_HIP(timed_launch(c, timed, s, "", flops, bytes, none, [&] { return launch_cdist(cp, bf16, s, &name, &shifted); }));
+    if (timed && c->recs.size() > nrec) c->recs.back().name = std::string(name) + (fuse ? "+select" : "");
     if (!shifted) {
       // row shifts of K^T: read the distances, write K and one shift per row
       const double cells = U * (double)plan.C;
-      WMD_HIP(timed_launch(c, s, "gibbs_rows_kernel", 2.0 * cells, 8.0 * cells + 4.0 * U * q->B, [&] {
-        return launch_gibbs_rows(kt, km, sp.qinfo, c->U, q->B, q->lambda, s);
+      const int max_S = (int)*std::max_element(plan.S.begin(), plan.S.end());
+      WMD_HIP(timed_launch(c, timed, s, "gibbs_rows_kernel", 2.0 * cells, 8.0 * cells + 4.0 * U * q->B, none, [&] {
+        return launch_gibbs_rows(kt, km, sp.qinfo, c->U, q->B, max_S, q->lambda, s);
       }));
     }
   }
@@ -450,170 +589,149 @@ static wmd_status enqueue_query(wmd_corpus* c, const wmd_query_desc* q, float* o
     WMD_HIP(launch_fill_i32(q->iters, n, schedule == WMD_SCHEDULE_RESIDENT ? 0 : q->max_iter, s));
   }
 
-  // a4-a6: Sinkhorn iterations and the final pass.  Per query, the length
-  // buckets that one-wave items hold share one launch; the others (and any
-  // bucket with a pinned shape) get launches of their own.  Launch units are
-  // independent of each other; with several they are spread over the side
-  // streams.
-  struct Unit {
-    bool merged = false;
-    MergePlan plan;
-    int off[kMergeMax] = {}, nd[kMergeMax] = {};
-    SinkConfig cfg{};
-    int bk = -1;
-    double nzb = 0.0, ndd = 0.0;
-    std::string name;
-  };
-  std::vector<std::vector<Unit>> units((size_t)q->B);
-  int groups = 0;
-  for (int b = 0; b < q->B; ++b) {
-    const int S = (int)plan.S[(size_t)b];
-    int caps[kNumBuckets], nds[kNumBuckets], bks[kNumBuckets], nm = 0;
-    for (int bk = 0; bk < kNumBuckets; ++bk) {
-      const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
-      if (nd == 0) continue;
-      caps[nm] = kBucketCap[bk]; nds[nm] = (int)nd; bks[nm] = bk; ++nm;
-    }
-    bool in_merge[kNumBuckets] = {};
-    MergePlan mp;
-    if (c->merge == WMD_MERGE_ALL && nm > 1 && plan_merge(S, caps, nds, nm, &mp) && mp.n > 1) {
-      Unit u;
-      u.merged = true;
-      u.plan = mp;
-      for (int g = 0; g < mp.n; ++g) {
-        const int bk = bks[mp.member[g]];
-        in_merge[bk] = true;
-        u.off[g] = (int)c->bucket_off[bk];
-        u.nd[g] = nds[mp.member[g]];
-        u.nzb += (double)c->bucket_nnz[bk];
-        u.ndd += (double)u.nd[g];
+  // a4-a6: Sinkhorn iterations and the final pass.  Resident schedule: the
+  // units of all queries with equal keys share one launch (at most
+  // kMaxLaunchQueries queries each), in order of first appearance; the other
+  // schedules (comparison baselines) and the streaming fallback launch per
+  // query.  Launches are independent of each other; with several they are
+  // spread over the caller stream's side streams.
+  struct Launch { const SinkUnit* u; std::vector<int> qs; };
+  std::vector<Launch> launches;
+  {
+    std::map<std::vector<int64_t>, size_t> open;  // key -> launch still taking queries
+    for (int b = 0; b < q->B; ++b)
+      for (const SinkUnit& u : *qunits[(size_t)b]) {
+        const bool share =
+            schedule == WMD_SCHEDULE_RESIDENT && !u.cfg.stream && !(q->flags & WMD_QUERY_PER_QUERY_LAUNCHES);
+        if (share) {
+          auto it = open.find(u.key);
+          if (it != open.end() && launches[it->second].qs.size() < (size_t)kMaxLaunchQueries) {
+            launches[it->second].qs.push_back(b);
+            continue;
+          }
+          open[u.key] = launches.size();
+        }
+        launches.push_back({&u, {b}});
       }
-      u.name = "sink_merge_kernel<" + std::to_string(mp.tc) + "," + std::to_string(mp.trmax) + "," +
-               std::to_string(mp.lg_cg) + ">x" + std::to_string(mp.n);
-      units[(size_t)b].push_back(std::move(u));
-    }
-    for (int bk = 0; bk < kNumBuckets; ++bk) {
-      const int64_t nd = c->bucket_off[bk + 1] - c->bucket_off[bk];
-      if (nd == 0 || in_merge[bk]) continue;
-      Unit u;
-      u.bk = bk;
-      auto pin = c->pinned.find({S, kBucketCap[bk]});
-      if (pin != c->pinned.end()) {
-        u.cfg = pin->second;
-      } else if (!choose_sink_config(S, kBucketCap[bk], (int)nd, &u.cfg)) {
-        return fail(WMD_ERR_NOT_SUPPORTED, "no kernel shape for query width " + std::to_string(S) +
-                                               " and documents of up to " + std::to_string(kBucketCap[bk]) + " words");
-      }
-      u.nzb = (double)c->bucket_nnz[bk];
-      u.ndd = (double)nd;
-      const SinkConfig& cfg = u.cfg;
-      u.name = cfg.stream ? std::string("sink_stream_kernel")
-                          : cfg.multiwave ? "sink_kernel<" + std::to_string(cfg.tc) + "," + std::to_string(cfg.tr) +
-                                                "," + std::to_string(cfg.lg_cg) + "," + std::to_string(cfg.maxw) +
-                                                ">x" + std::to_string(cfg.nwaves)
-                                          : "sink_merge_kernel<" + std::to_string(cfg.tc) + "," +
-                                                std::to_string(cfg.tr) + "," + std::to_string(cfg.lg_cg) + ">x1";
-      units[(size_t)b].push_back(std::move(u));
-    }
-    groups += (int)units[(size_t)b].size();
   }
+  const int groups = (int)launches.size();
   // inside a graph, branches cost nothing on the host; eagerly, the event
   // traffic only pays off with more groups
-  const bool fork = in_graph ? groups > 1 : groups > 3;
+  const bool fork = side && (in_graph ? groups > 1 : groups > 3);
   // side streams in use: every one that waits on the fork must be joined
   // again (a stream left out of the join would end a capture unjoined)
   const int nside = fork ? std::min(groups, wmd_corpus::kSide) : 0;
-  std::unique_lock<std::mutex> side_lock(c->side_mu, std::defer_lock);
   if (fork) {
-    side_lock.lock();
-    WMD_HIP(hipEventRecord(c->fork_ev, s));
-    for (int i = 0; i < nside; ++i) WMD_HIP(hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
+    WMD_HIP(hipEventRecord(side->fork_ev, s));
+    for (int i = 0; i < nside; ++i) WMD_HIP(hipStreamWaitEvent(side->side[i], side->fork_ev, 0));
   }
   float* ubuf = at<float>(ws, L.u);
   float* wbuf = at<float>(ws, L.w);
   const int4* drec = at<int4>(c->ws, CL.drec);
-  int group = 0;
-  for (int b = 0; b < q->B; ++b) {
+  // parameters of query b (base + b for a query set's base: b = 0)
+  auto params_of = [&](int b) {
     const int64_t col0 = plan.col0[(size_t)b];
-    const int S = (int)plan.S[(size_t)b];
-    float* orow = out + (size_t)b * (size_t)c->N;
     SinkParams p{};
     p.kt = kt + (size_t)col0 * (size_t)c->U;
     p.km = km + (size_t)b * (size_t)c->U;
     p.r = sp.r + col0;
     p.vr = sp.vr + b;
     p.wl = at<int>(c->ws, CL.wl); p.wn = at<float>(c->ws, CL.wn);
-    p.S = S;
+    p.S = (int)plan.S[(size_t)b];
     p.inv_lam = 1.0f / q->lambda;
     p.tol = q->tol;
     p.iters_out = (q->iters && schedule == WMD_SCHEDULE_RESIDENT) ? q->iters + (size_t)b * (size_t)c->N : nullptr;
-    p.out = orow;
+    p.out = out + (size_t)b * (size_t)c->N;
     p.u = ubuf + (size_t)col0 * (size_t)c->N;
     p.w = wbuf + (size_t)b * (size_t)c->nnz;
-    const double vrq = (double)(q->q_ptr_host[b + 1] - q->q_ptr_host[b]);
-    for (const Unit& u : units[(size_t)b]) {
-      hipStream_t gs = fork ? c->side[group % nside] : s;
-      ++group;
-      c->tag_query = b; c->tag_S = S;
-      c->tag_cap = u.merged ? 0 : kBucketCap[u.bk];
-      c->tag_ndocs = (int)u.ndd;
-      auto launch = [&](const SinkParams& a) -> hipError_t {
-        if (u.merged) {
-          SinkParams m = a;
-          m.drec = drec;
-          int grid = 0;
-          return launch_sink_merged(m, u.plan, u.off, u.nd, gs, &grid);
-        }
-        SinkParams one = a;
-        one.drec = drec + c->bucket_off[u.bk];
-        one.ndocs = (int)u.ndd;
-        return launch_sink(one, u.cfg, sink_grid(u.cfg, one.ndocs), gs);
-      };
-      // algorithmic work per document and iteration (n_k entries, v_r query words):
-      // 4 v_r n_k + n_k + 2 v_r flops; 8 n_k + 4 v_r n_k + 8 v_r bytes when u and the
-      // K^T rows travel through memory every pass.  The final pass does
-      // 4 v_r n_k + 2 n_k flops.
-      const double nzb = u.nzb, ndd = u.ndd;
-      const double it_flops = 4.0 * vrq * nzb + nzb + 2.0 * vrq * ndd;
-      const double it_bytes = 8.0 * nzb + 4.0 * vrq * nzb + 8.0 * vrq * ndd;
-      const double fin_flops = 4.0 * vrq * nzb + 2.0 * nzb;
-      auto go = [&](const SinkParams& a, double fl, double by) {
-        return timed_launch(c, gs, u.name, fl, by, [&] { return launch(a); });
-      };
-      if (schedule == WMD_SCHEDULE_RESIDENT) {
-        SinkParams a = p;
-        a.iters = q->max_iter; a.do_final = 1;
-        // resident: the entries, the document records and the K^T rows are read once
-        WMD_HIP(go(a, q->max_iter * it_flops + fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 20.0 * ndd));
-      } else {
-        for (int it = 0; it < q->max_iter; ++it) {
-          if (schedule == WMD_SCHEDULE_PER_ITERATION) {
-            SinkParams a = p;
-            a.iters = 1; a.load_u = it > 0; a.store_u = 1;
-            WMD_HIP(go(a, it_flops, it_bytes));
-          } else {
-            SinkParams a = p;  // SDDMM: w_j = c_j / (K_j . u)
-            a.iters = 1; a.load_u = it > 0; a.store_w = 1;
-            WMD_HIP(go(a, 2.0 * vrq * nzb + nzb, 12.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd));
-            SinkParams m = p;  // SpMM: acc = K w, u = r / acc
-            m.iters = 1; m.load_w = 1; m.store_u = 1;
-            WMD_HIP(go(m, 2.0 * vrq * nzb + 2.0 * vrq * ndd, 8.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd));
-          }
-        }
-        SinkParams f = p;
-        f.iters = 0; f.load_u = q->max_iter > 0; f.do_final = 1;
-        WMD_HIP(go(f, fin_flops, 8.0 * nzb + 4.0 * vrq * nzb + 4.0 * vrq * ndd + 20.0 * ndd));
+    return p;
+  };
+  int group = 0;
+  for (const Launch& ln : launches) {
+    const SinkUnit& u = *ln.u;
+    hipStream_t gs = fork ? side->side[group % nside] : s;
+    ++group;
+    const int b0 = ln.qs[0];
+    const bool multi = ln.qs.size() > 1;
+    SinkQuerySet qset{};
+    if (multi) {
+      qset.nq = (int)ln.qs.size();
+      qset.U = c->U;
+      qset.N = c->N;
+      for (size_t i = 0; i < ln.qs.size(); ++i) {
+        const int b = ln.qs[i];
+        qset.q[i] = make_int4(b, (int)plan.col0[(size_t)b], (int)plan.S[(size_t)b], 0);
       }
     }
-    c->tag_query = b; c->tag_S = 0; c->tag_cap = 0; c->tag_ndocs = (int)c->empty_count;
-    if (c->empty_count > 0)
-      WMD_HIP(timed_launch(c, s, "nan_docs_kernel", 0.0, 8.0 * c->empty_count,
-                           [&] { return launch_nan_docs(c->docs() + c->empty_off, c->empty_count, orow, s); }));
+    const SinkParams p = multi ? params_of(0) : params_of(b0);
+    Tag tag{b0, (int)plan.S[(size_t)b0], u.merged ? 0 : kBucketCap[u.bk[0]], (int)u.ndd};
+    auto launch = [&](const SinkParams& a) -> hipError_t {
+      if (u.merged) {
+        SinkParams m = a;
+        m.drec = drec;
+        int off[kMergeMax], nd[kMergeMax];
+        for (int g = 0; g < u.nb; ++g) {
+          off[g] = (int)c->bucket_off[u.bk[g]];
+          nd[g] = (int)(c->bucket_off[u.bk[g] + 1] - c->bucket_off[u.bk[g]]);
+        }
+        int grid = 0;
+        return launch_sink_merged(m, u.plan, off, nd, gs, &grid, multi ? &qset : nullptr);
+      }
+      SinkParams one = a;
+      one.drec = drec + c->bucket_off[u.bk[0]];
+      one.ndocs = (int)u.ndd;
+      return launch_sink(one, u.cfg, sink_grid(u.cfg, one.ndocs), gs, multi ? &qset : nullptr);
+    };
+    // algorithmic work per document and iteration (n_k entries, v_r query words):
+    // 4 v_r n_k + n_k + 2 v_r flops; 8 n_k + 4 v_r n_k + 8 v_r bytes when u and the
+    // K^T rows travel through memory every pass.  The final pass does
+    // 4 v_r n_k + 2 n_k flops.  Summed over the launch's queries.
+    const double nzb = u.nzb, ndd = u.ndd;
+    double vsum = 0.0;
+    for (int b : ln.qs) vsum += (double)(q->q_ptr_host[b + 1] - q->q_ptr_host[b]);
+    const double nq = (double)ln.qs.size();
+    const double it_flops = 4.0 * vsum * nzb + nq * nzb + 2.0 * vsum * ndd;
+    const double it_bytes = 8.0 * nq * nzb + 4.0 * vsum * nzb + 8.0 * vsum * ndd;
+    const double fin_flops = 4.0 * vsum * nzb + 2.0 * nq * nzb;
+    auto go = [&](const SinkParams& a, double fl, double by) {
+      return timed_launch(c, timed, gs, u.name, fl, by, tag, [&] { return launch(a); });
+    };
+    if (schedule == WMD_SCHEDULE_RESIDENT) {
+      SinkParams a = p;
+      a.iters = q->max_iter; a.do_final = 1;
+      // resident: the entries, the document records and the K^T rows are read once
+      WMD_HIP(go(a, q->max_iter * it_flops + fin_flops, 8.0 * nq * nzb + 4.0 * vsum * nzb + 20.0 * nq * ndd));
+    } else {
+      for (int it = 0; it < q->max_iter; ++it) {
+        if (schedule == WMD_SCHEDULE_PER_ITERATION) {
+          SinkParams a = p;
+          a.iters = 1; a.load_u = it > 0; a.store_u = 1;
+          WMD_HIP(go(a, it_flops, it_bytes));
+        } else {
+          SinkParams a = p;  // SDDMM: w_j = c_j / (K_j . u)
+          a.iters = 1; a.load_u = it > 0; a.store_w = 1;
+          WMD_HIP(go(a, 2.0 * vsum * nzb + nq * nzb, 12.0 * nq * nzb + 4.0 * vsum * nzb + 4.0 * vsum * ndd));
+          SinkParams m = p;  // SpMM: acc = K w, u = r / acc
+          m.iters = 1; m.load_w = 1; m.store_u = 1;
+          WMD_HIP(go(m, 2.0 * vsum * nzb + 2.0 * vsum * ndd, 8.0 * nq * nzb + 4.0 * vsum * nzb + 4.0 * vsum * ndd));
+        }
+      }
+      SinkParams f = p;
+      f.iters = 0; f.load_u = q->max_iter > 0; f.do_final = 1;
+      WMD_HIP(go(f, fin_flops, 8.0 * nq * nzb + 4.0 * vsum * nzb + 4.0 * vsum * ndd + 20.0 * nq * ndd));
+    }
   }
+  if (c->empty_count > 0)
+    for (int b = 0; b < q->B; ++b) {
+      const Tag tag{b, 0, 0, (int)c->empty_count};
+      WMD_HIP(timed_launch(c, timed, s, "nan_docs_kernel", 0.0, 8.0 * c->empty_count, tag, [&] {
+        return launch_nan_docs(c->docs() + c->empty_off, c->empty_count, out + (size_t)b * (size_t)c->N, s);
+      }));
+    }
   if (fork)
     for (int i = 0; i < nside; ++i) {
-      WMD_HIP(hipEventRecord(c->join_ev[i], c->side[i]));
-      WMD_HIP(hipStreamWaitEvent(s, c->join_ev[i], 0));
+      WMD_HIP(hipEventRecord(side->join_ev[i], side->side[i]));
+      WMD_HIP(hipStreamWaitEvent(s, side->join_ev[i], 0));
     }
   return WMD_OK;
 }
@@ -622,13 +740,16 @@ wmd_status wmd_set_merge(wmd_corpus* c, int32_t mode) {
   g_err.clear();
   if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
   if (mode != WMD_MERGE_ALL && mode != WMD_MERGE_NONE) return fail(WMD_ERR_INVALID_ARGUMENT, "unknown merge mode");
+  std::lock_guard<std::mutex> lock(c->cfg_mu);
   c->merge = mode;
+  c->plans.clear();
   return WMD_OK;
 }
 
 wmd_status wmd_set_timing(wmd_corpus* c, int32_t enable) {
   g_err.clear();
   if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
+  std::lock_guard<std::mutex> lock(c->timing_mu);
   c->timing = enable != 0;
   c->recs.clear();
   return WMD_OK;
@@ -637,6 +758,7 @@ wmd_status wmd_set_timing(wmd_corpus* c, int32_t enable) {
 wmd_status wmd_get_timing(wmd_corpus* c, wmd_kernel_stat* stats, int32_t capacity, int32_t* count) {
   g_err.clear();
   if (!c || !count || (capacity > 0 && !stats)) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::lock_guard<std::mutex> lock(c->timing_mu);
   std::vector<std::string> names;
   std::vector<wmd_kernel_stat> acc;
   for (const auto& r : c->recs) {
@@ -671,27 +793,46 @@ static uint64_t bits_of(float f) {
 wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* workspace, size_t workspace_bytes,
                      void* stream) {
   g_err.clear();
-  if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
-  const bool graph = (q->flags & WMD_QUERY_GRAPH) && stream != nullptr && !c->timing;
-  if (!graph) return enqueue_query(c, q, out, workspace, workspace_bytes, stream, false);
+  wmd_status st = check_query_desc(c, q, out, workspace);
+  if (st != WMD_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // a timed call holds timing_mu throughout (its records and event pool are shared)
+  std::unique_lock<std::mutex> timing_lock(c->timing_mu, std::defer_lock);
+  bool timed = c->timing.load();
+  if (timed) {
+    timing_lock.lock();
+    timed = c->timing.load();
+    if (!timed) timing_lock.unlock();
+  }
+  wmd_corpus::SideSet* side = nullptr;
+  st = side_set(c, s, &side);
+  if (st != WMD_OK) return st;
+  // the side set stays locked until the call's launches (or its capture) are complete
+  std::unique_lock<std::mutex> side_lock;
+  if (side) side_lock = std::unique_lock<std::mutex>(side->mu);
+  const bool graph = (q->flags & WMD_QUERY_GRAPH) && stream != nullptr && !timed;
+  if (!graph) return enqueue_query(c, q, out, workspace, workspace_bytes, stream, false, side, timed);
   if (q->B < 1 || !q->q_ptr_host) return fail(WMD_ERR_INVALID_ARGUMENT, "B must be >= 1 with host offsets");
   // every argument the captured launches depend on
   std::vector<uint64_t> key = {(uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)workspace, (uint64_t)workspace_bytes,
                                (uint64_t)(uintptr_t)q->q_ptr, (uint64_t)(uintptr_t)q->q_ids,
                                (uint64_t)(uintptr_t)q->q_weights, (uint64_t)(uintptr_t)q->iters,
                                (uint64_t)q->B, bits_of(q->lambda), (uint64_t)q->max_iter, (uint64_t)q->cdist,
-                               (uint64_t)q->schedule, bits_of(q->tol)};
-  key.push_back((uint64_t)c->merge);
+                               (uint64_t)q->schedule, bits_of(q->tol), (uint64_t)(uintptr_t)stream,
+                               (uint64_t)q->flags};
   for (int b = 0; b <= q->B; ++b) key.push_back((uint64_t)q->q_ptr_host[b]);
-  for (const auto& p : c->pinned) {
-    key.push_back(((uint64_t)p.first.first << 32) | (uint32_t)p.first.second);
-    key.push_back(((uint64_t)p.second.tc << 48) | ((uint64_t)p.second.tr << 32) | ((uint64_t)p.second.lg_cg << 16) |
-                  ((uint64_t)p.second.nwaves << 8) | (uint64_t)p.second.maxw);
+  {
+    std::lock_guard<std::mutex> lock(c->cfg_mu);
+    key.push_back((uint64_t)c->merge);
+    for (const auto& p : c->pinned) {
+      key.push_back(((uint64_t)p.first.first << 32) | (uint32_t)p.first.second);
+      key.push_back(((uint64_t)p.second.tc << 48) | ((uint64_t)p.second.tr << 32) |
+                    ((uint64_t)p.second.lg_cg << 16) | ((uint64_t)p.second.nwaves << 8) | (uint64_t)p.second.maxw);
+    }
   }
   int dev = 0;
   WMD_HIP(hipGetDevice(&dev));
   if (dev != c->device) return fail(WMD_ERR_INVALID_ARGUMENT, "current device differs from the corpus device");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> graph_lock(c->graph_mu);
   for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
     if (it->key != key) continue;
@@ -700,7 +841,7 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
     return WMD_OK;
   }
   WMD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-  wmd_status st = enqueue_query(c, q, out, workspace, workspace_bytes, stream, true);
+  st = enqueue_query(c, q, out, workspace, workspace_bytes, stream, true, side, false);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (st != WMD_OK) {
@@ -727,6 +868,7 @@ wmd_status wmd_query(wmd_corpus* c, const wmd_query_desc* q, float* out, void* w
 wmd_status wmd_get_launches(wmd_corpus* c, wmd_launch_rec* recs, int32_t capacity, int32_t* count) {
   g_err.clear();
   if (!c || !count || (capacity > 0 && !recs)) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::lock_guard<std::mutex> lock(c->timing_mu);
   int32_t n = 0;
   for (const auto& r : c->recs) {
     if (n < capacity) {
@@ -769,13 +911,17 @@ wmd_status wmd_set_sink_shape(wmd_corpus* c, int32_t S, int32_t cap, const wmd_s
   g_err.clear();
   if (!c) return fail(WMD_ERR_INVALID_ARGUMENT, "corpus is NULL");
   if (!shape) {
+    std::lock_guard<std::mutex> lock(c->cfg_mu);
     c->pinned.erase({S, cap});
+    c->plans.clear();
     return WMD_OK;
   }
   SinkConfig cfg{shape->tc, shape->tr, shape->lg_cg, shape->nwaves, shape->maxw > 1, shape->stream != 0, shape->maxw};
   if (cfg.stream) cfg = SinkConfig{0, 0, 6, 4, false, true, 4};
   if (!sink_config_fits(cfg, S, cap)) return fail(WMD_ERR_INVALID_ARGUMENT, "shape cannot run this (S, cap)");
+  std::lock_guard<std::mutex> lock(c->cfg_mu);
   c->pinned[{S, cap}] = cfg;
+  c->plans.clear();
   return WMD_OK;
 }
 
@@ -783,24 +929,23 @@ size_t wmd_query_static_capacity(void) { return kScratchBytes; }
 
 wmd_status wmd_query_static(wmd_corpus* c, const wmd_query_desc* q, float* out, void* stream) {
   g_err.clear();
-  if (!c || !q) return fail(WMD_ERR_INVALID_ARGUMENT, "NULL corpus or query descriptor");
+  wmd_status st = check_query_desc(c, q, out, c ? c->scratch : nullptr);
+  if (st != WMD_OK) return st;
   if (q->flags & WMD_QUERY_GRAPH)
     return fail(WMD_ERR_NOT_SUPPORTED, "wmd_query_static does not capture graphs (instantiating one allocates)");
   if (c->timing)
     return fail(WMD_ERR_NOT_SUPPORTED, "wmd_query_static does not run while per-kernel timing is enabled");
-  if (!c->scratch) return fail(WMD_ERR_DEVICE, "static scratch of the corpus device is not resolved");
   QueryPlan plan;
-  wmd_status st = plan_query(c, q->B, q->q_ptr_host, &plan);
+  st = plan_query(c, q->B, q->q_ptr_host, &plan);
   if (st != WMD_OK) return st;
-  if (q->schedule < WMD_SCHEDULE_AUTO || q->schedule > WMD_SCHEDULE_UNFUSED)
-    return fail(WMD_ERR_INVALID_ARGUMENT, "unknown schedule");
   const int schedule = q->schedule == WMD_SCHEDULE_AUTO ? WMD_SCHEDULE_RESIDENT : q->schedule;
   const size_t need = layout_for(c, plan, schedule).total;
   if (need > kScratchBytes)
     return fail(WMD_ERR_NOT_SUPPORTED, "this call needs " + std::to_string(need) +
                                            " bytes of query workspace; the static scratch holds " +
                                            std::to_string(kScratchBytes) + " (use wmd_query with a workspace)");
-  return enqueue_query(c, q, out, c->scratch, kScratchBytes, stream, false);
+  // no side streams: creating a caller stream's set would create streams
+  return enqueue_query(c, q, out, c->scratch, kScratchBytes, stream, false, nullptr, false);
 }
 
 wmd_status wmd_query_errors(const void* workspace, int32_t B, int32_t* codes, void* stream) {

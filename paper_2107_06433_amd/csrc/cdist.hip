@@ -721,11 +721,15 @@ hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const ch
 // Row shift for calls whose cost-matrix kernel stored plain distances (see
 // CdistParams): per query b and row j, m_j = min over the query's columns,
 // K = exp(-lambda (M - m_j)), +inf (an unused slot) -> 1.  A row of S floats
-// takes L = S/4 lanes rounded up to a power of two (at most 64, then the lanes
-// loop over the row), one 16-byte piece per lane and step; 64 / L rows per
-// wave.
+// takes L = S/4 lanes rounded up to a power of two (at most 64), one 16-byte
+// piece per lane and step, 64 / L rows per wave.  The waves of a query's
+// blocks stride over its row groups, four groups at a time so that four
+// loads per lane are in flight; the first two pieces of every lane stay in
+// registers between the minimum and the rewrite (longer rows, S > 512, read
+// the rest twice).
 __global__ void __launch_bounds__(256) gibbs_rows_kernel(float* kt, float* km, const int2* qinfo, int64_t U,
                                                         float lam) {
+  constexpr int G = 4;  // row groups per pass
   const int b = blockIdx.y;
   const int2 qi = qinfo[b];
   const int S = qi.y;
@@ -735,37 +739,64 @@ __global__ void __launch_bounds__(256) gibbs_rows_kernel(float* kt, float* km, c
   const int L = 1 << lg, R = 64 >> lg;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane & (L - 1), rw = lane >> lg;
-  float* blk = kt + (size_t)qi.x * (size_t)U;
   constexpr float kInf = __builtin_huge_valf();
-  for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * R; r0 < U; r0 += (int64_t)gridDim.x * 4 * R) {
-    const int64_t row = r0 + rw;
-    const bool ok = row < U;
-    float4* rp = (float4*)(blk + (size_t)(ok ? row : 0) * S);
-    float mn = kInf;
-    for (int c = sub; c < n4; c += L) {
-      const float4 v = rp[c];
-      mn = fminf(fminf(mn, v.x), fminf(v.y, fminf(v.z, v.w)));
+  float* blk = kt + (size_t)qi.x * (size_t)U;
+  const int64_t step = (int64_t)gridDim.x * 4 * R;  // rows between a wave's consecutive groups
+  for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * R; r0 < U; r0 += G * step) {
+    float4 v0[G], v1[G];
+    float mn[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t row = r0 + g * step + rw;
+      float4* rp = (float4*)(blk + (size_t)(row < U ? row : 0) * S);
+      v0[g] = v1[g] = make_float4(kInf, kInf, kInf, kInf);
+      if (sub < n4) v0[g] = rp[sub];
+      if (sub + L < n4) v1[g] = rp[sub + L];
     }
-    for (int o = 1; o < L; o <<= 1) mn = fminf(mn, __shfl_xor(mn, o));
-    mn = mn < kInf ? mn : 0.f;
-    if (ok) {
-      for (int c = sub; c < n4; c += L) {
-        float4 v = rp[c];
-        v.x = v.x < kInf ? expf(-lam * (v.x - mn)) : 1.f;
-        v.y = v.y < kInf ? expf(-lam * (v.y - mn)) : 1.f;
-        v.z = v.z < kInf ? expf(-lam * (v.z - mn)) : 1.f;
-        v.w = v.w < kInf ? expf(-lam * (v.w - mn)) : 1.f;
-        rp[c] = v;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t row = r0 + g * step + rw;
+      float4* rp = (float4*)(blk + (size_t)(row < U ? row : 0) * S);
+      float m = fminf(fminf(fminf(v0[g].x, v0[g].y), fminf(v0[g].z, v0[g].w)),
+                      fminf(fminf(v1[g].x, v1[g].y), fminf(v1[g].z, v1[g].w)));
+      for (int c = sub + 2 * L; c < n4; c += L) {
+        const float4 v = rp[c];
+        m = fminf(m, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
       }
-      if (sub == 0) km[(size_t)b * (size_t)U + row] = mn;
+      for (int o = 1; o < L; o <<= 1) m = fminf(m, __shfl_xor(m, o));
+      mn[g] = m < kInf ? m : 0.f;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t row = r0 + g * step + rw;
+      if (row >= U) continue;
+      float4* rp = (float4*)(blk + (size_t)row * S);
+      const float m = mn[g];
+      auto gibbs = [&](float4 v) {
+        v.x = v.x < kInf ? expf(-lam * (v.x - m)) : 1.f;
+        v.y = v.y < kInf ? expf(-lam * (v.y - m)) : 1.f;
+        v.z = v.z < kInf ? expf(-lam * (v.z - m)) : 1.f;
+        v.w = v.w < kInf ? expf(-lam * (v.w - m)) : 1.f;
+        return v;
+      };
+      if (sub < n4) rp[sub] = gibbs(v0[g]);
+      if (sub + L < n4) rp[sub + L] = gibbs(v1[g]);
+      for (int c = sub + 2 * L; c < n4; c += L) rp[c] = gibbs(rp[c]);
+      if (sub == 0) km[(size_t)b * (size_t)U + row] = m;
     }
   }
 }
 
-hipError_t launch_gibbs_rows(float* kt, float* km, const int2* qinfo, int64_t U, int B, float lam, hipStream_t s) {
+hipError_t launch_gibbs_rows(float* kt, float* km, const int2* qinfo, int64_t U, int B, int max_S, float lam,
+                             hipStream_t s) {
   if (U <= 0 || B <= 0) return hipSuccess;
-  const int64_t gx = (U + 255) / 256;
-  dim3 grid((unsigned)(gx < 4096 ? gx : 4096), (unsigned)B);
+  int lg = 0;
+  while ((1 << lg) < (max_S >> 2) && lg < 6) ++lg;
+  // about 8192 blocks in all, at most one row group per wave of the widest query
+  const int64_t need = (U + 4 * (64 >> lg) - 1) / (4 * (64 >> lg));
+  int64_t gx = (8192 + B - 1) / B;
+  gx = gx < need ? gx : need;
+  dim3 grid((unsigned)(gx < 1 ? 1 : gx), (unsigned)B);
   gibbs_rows_kernel<<<grid, 256, 0, s>>>(kt, km, qinfo, U, lam);
   return hipGetLastError();
 }

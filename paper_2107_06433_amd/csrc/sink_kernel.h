@@ -355,13 +355,42 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       wid[t] = c > 0.f ? id : -1;
       cw[t] = c > 0.f ? c : 0.f;
     }
-    // sum_j c_j m_j of this lane's rows (column lane 0 of each row adds it):
-    // the part of d_k that the row scaling of K^T took out of the stored rows
+
+    // sum_j c_j m_j over the item's rows: the part of d_k that the row
+    // scaling of K^T took out of the stored rows (M_ij = m_j - ln(K_ij) /
+    // lambda).  The CG column lanes of a row lane share its rows, so row t is
+    // loaded and added by column lane t mod CG only: ceil(TR / CG) loads per
+    // lane, issued with the rows of K^T (loads return in order, so they wait
+    // for nothing the first iteration does not need anyway) and summed before
+    // the iterations.
     float cm = 0.f;
+    auto shift_sum = [&](auto load) {
+      constexpr int PER = (TR + CG - 1) / CG;
 #pragma unroll
-    for (int t = 0; t < TR; ++t) {
-      const float mj = p.km[wid[t] < 0 ? 0 : wid[t]];
-      cm = fmaf(cg == 0 ? cw[t] : 0.f, mj, cm);
+      for (int i = 0; i < PER; ++i) {
+        int id = -1;
+        float c = 0.f;
+#pragma unroll
+        for (int t = i * CG; t < TR && t < (i + 1) * CG; ++t) {
+          const bool mine = t - i * CG == cg;
+          id = mine ? wid[t] : id;
+          c = mine ? cw[t] : c;
+        }
+        cm = fmaf(c, load(p.km + (id < 0 ? 0 : id)), cm);
+      }
+    };
+    if constexpr (MW) {
+      // rows t = cg, cg + CG, ...: their entries read again (cache hits) rather
+      // than picked out of the row registers, which would need a mask per row
+      constexpr int PER = (TR + CG - 1) / CG;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int t = cg + CG * i, j = rs + RS * t;
+        const bool ok = t < TR && j < n;
+        const int id = ok ? p.wl[beg + j] : 0;
+        const float c = ok ? p.wn[beg + j] : 0.f;
+        cm = fmaf(c > 0.f ? c : 0.f, p.km[id], cm);
+      }
     }
     // Columns of lane cg: the 4-column chunks cg, cg + CG, ... (4 TC4 columns,
     // one 16-byte load per row each: S and every K^T row start are multiples
@@ -390,6 +419,11 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         K[t][e] = (wid[t] >= 0 && col < S) ? v : 1.f;
       }
     }
+    if constexpr (!MW) shift_sum([](const float* a) { return *a; });
+    // cm is complete here, with nothing waited for that the rows do not need
+    // (this keeps the compiler from carrying the loaded values, or the row
+    // ids, into the iterations)
+    asm volatile("" : "+v"(cm));
     float rv[TC], u[TC];
 #pragma unroll
     for (int e = 0; e < TC; ++e) {
@@ -632,7 +666,6 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
       float part[1] = {0.f};
 #pragma unroll
       for (int t = 0; t < TR; ++t) part[0] = fmaf(wf[t], sb[t], part[0]);
-      // M_ij = m_j - ln(K_ij) / lambda for the row-scaled K
       part[0] = fmaf(part[0], kNegLn2 * p.inv_lam, cm);
       sum_low<HALF ? 5 : 6>(part);
       float tot = part[0];
@@ -657,23 +690,32 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
 // has a block per document, a block whose document fits in 3/4 of its rows
 // runs a body of 3TR/4 rows per lane (see sink_body_fit); the choice is the
 // same for every wave of the block, so its barriers stay matched.
+// With a query set the grid is nq runs of the per-query grid.
 template <int TC, int TR, int LG_CG, int MAXW, bool RES>
-__global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p) {
+__global__ void __launch_bounds__(64 * MAXW) sink_kernel(SinkParams p, SinkQuerySet qs) {
+  int blk = blockIdx.x, nblk = gridDim.x;
+  if (qs.nq > 0) {
+    const int per = nblk / qs.nq;
+    const int qi = blk / per;
+    blk -= qi * per;
+    nblk = per;
+    p = for_query(p, qs, qi);
+  }
   if constexpr (TR >= 4) {
-    if ((int)gridDim.x >= p.ndocs) {
+    if (nblk >= p.ndocs) {
       constexpr int T3 = 3 * TR / 4;
-      const int item = blockIdx.x;
+      const int item = blk;
       const int4 rec = item < p.ndocs ? p.drec[item] : make_int4(0, 0, 0, 0);
       const int rows = (int)(blockDim.x >> 6) * (64 >> LG_CG) * T3;
       if (rec.z <= rows) {
-        sink_body<TC, T3, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x, &rec);
+        sink_body<TC, T3, LG_CG, MAXW, RES>(p, blk, nblk, &rec);
       } else {
-        sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x, &rec);
+        sink_body<TC, TR, LG_CG, MAXW, RES>(p, blk, nblk, &rec);
       }
       return;
     }
   }
-  sink_body<TC, TR, LG_CG, MAXW, RES>(p, blockIdx.x, gridDim.x);
+  sink_body<TC, TR, LG_CG, MAXW, RES>(p, blk, nblk);
 }
 
 // T rows per lane hold documents of up to (lanes per item >> lg_cg) * T
@@ -706,8 +748,9 @@ __device__ __forceinline__ void sink_body_fit(const SinkParams& p, int blk, int 
 }
 
 // One-wave items, four per block (eight as half-wave items), for several
-// length buckets of one query in a single launch.  Group g holds blocks
-// [end[g-1], end[g]) and documents drec[off[g]] ... drec[off[g] + ndocs[g] - 1];
+// length buckets of one query (or of each query of a set) in a single launch.
+// Group g holds blocks [end[g-1], end[g]) -- with a query set, nq equal runs,
+// one per query -- and documents drec[off[g]] ... drec[off[g] + ndocs[g] - 1];
 // body[g] & 3 = 0, 1, 2 gives its rows per lane TRMAX, TRMAX/2 or TRMAX/4, and
 // body[g] & 4 makes its items half-wave (two per wave, 32 lanes each).
 // Groups come longest documents first, so the longest items start first and
@@ -732,6 +775,14 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
       b1 = m.end[i];
     }
   SinkParams p = m.p;
+  int blk = b - b0, nblk = b1 - b0;
+  if (m.qs.nq > 0) {
+    const int per = nblk / m.qs.nq;  // this group's blocks for one query
+    const int qi = blk / per;
+    blk -= qi * per;
+    nblk = per;
+    p = for_query(p, m.qs, qi);
+  }
   p.drec += off;
   p.ndocs = nd;
   const bool half = (body & 4) != 0;
@@ -739,24 +790,24 @@ __global__ void __launch_bounds__(256) sink_merge_kernel(SinkMerge m) {
   if constexpr (LG_CG <= 4) {
     if (half) {
       if (shift == 0) {
-        sink_body_fit<TC, TRMAX, LG_CG, RES, true>(p, b - b0, b1 - b0);
+        sink_body_fit<TC, TRMAX, LG_CG, RES, true>(p, blk, nblk);
       } else if constexpr (TRMAX >= 2) {
         if (shift == 1) {
-          sink_body_fit<TC, TRMAX / 2, LG_CG, RES, true>(p, b - b0, b1 - b0);
+          sink_body_fit<TC, TRMAX / 2, LG_CG, RES, true>(p, blk, nblk);
         } else if constexpr (TRMAX >= 4) {
-          sink_body_fit<TC, TRMAX / 4, LG_CG, RES, true>(p, b - b0, b1 - b0);
+          sink_body_fit<TC, TRMAX / 4, LG_CG, RES, true>(p, blk, nblk);
         }
       }
       return;
     }
   }
   if (shift == 0) {
-    sink_body_fit<TC, TRMAX, LG_CG, RES, false>(p, b - b0, b1 - b0);
+    sink_body_fit<TC, TRMAX, LG_CG, RES, false>(p, blk, nblk);
   } else if constexpr (TRMAX >= 2) {
     if (shift == 1) {
-      sink_body_fit<TC, TRMAX / 2, LG_CG, RES, false>(p, b - b0, b1 - b0);
+      sink_body_fit<TC, TRMAX / 2, LG_CG, RES, false>(p, blk, nblk);
     } else if constexpr (TRMAX >= 4) {
-      sink_body_fit<TC, TRMAX / 4, LG_CG, RES, false>(p, b - b0, b1 - b0);
+      sink_body_fit<TC, TRMAX / 4, LG_CG, RES, false>(p, blk, nblk);
     }
   }
 }

@@ -276,26 +276,33 @@ bool choose_sink_config(int S, int cap, int ndocs, SinkConfig* out) {
   return true;
 }
 
-hipError_t launch_sink(const SinkParams& p, const SinkConfig& c, int grid, hipStream_t s) {
+hipError_t launch_sink(const SinkParams& p, const SinkConfig& c, int grid, hipStream_t s, const SinkQuerySet* qs) {
+  const int nq = qs ? qs->nq : 0;
+  if (nq < 0 || nq > kMaxLaunchQueries) return hipErrorInvalidValue;
   if (c.stream) {
+    if (nq > 0) return hipErrorInvalidValue;  // the fallback runs one query per launch
     if (p.S > kStreamMaxS) return hipErrorInvalidValue;
     sink_stream_kernel<<<grid, 256, 0, s>>>(p);
     return hipGetLastError();
   }
   const Shape* sh = find_shape(c);
   if (!sh) return hipErrorInvalidValue;
+  const int total = grid * (nq > 0 ? nq : 1);
   if (sh->e.maxw == 1) {  // a merged launch with a single group
     SinkMerge m{};
     m.p = p;
+    if (qs) m.qs = *qs;
     m.ngroups = 1;
-    m.end[0] = grid;
+    m.end[0] = total;
     m.ndocs[0] = p.ndocs;
     void* args[] = {&m};
-    return hipLaunchKernel(kernel_for(*sh, p), dim3(grid), dim3(256), args, 0, s);
+    return hipLaunchKernel(kernel_for(*sh, p), dim3(total), dim3(256), args, 0, s);
   }
   SinkParams a = p;
-  void* args[] = {&a};
-  return hipLaunchKernel(kernel_for(*sh, p), dim3(grid), dim3(sink_block(c)), args, lds_bytes(c), s);
+  SinkQuerySet q{};
+  if (qs) q = *qs;
+  void* args[] = {&a, &q};
+  return hipLaunchKernel(kernel_for(*sh, p), dim3(total), dim3(sink_block(c)), args, lds_bytes(c), s);
 }
 
 namespace {
@@ -404,17 +411,19 @@ bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out)
 }
 
 hipError_t launch_sink_merged(const SinkParams& p, const MergePlan& plan, const int* off, const int* ndocs,
-                              hipStream_t s, int* grid_out) {
+                              hipStream_t s, int* grid_out, const SinkQuerySet* qs) {
   SinkConfig c{plan.tc, plan.trmax, plan.lg_cg, 1, false, false, 1};
   const Shape* sh = find_shape(c);
-  if (!sh || plan.n < 1 || plan.n > kMergeMax) return hipErrorInvalidValue;
+  const int nq = qs ? qs->nq : 0;
+  if (!sh || plan.n < 1 || plan.n > kMergeMax || nq < 0 || nq > kMaxLaunchQueries) return hipErrorInvalidValue;
   SinkMerge m{};
   m.p = p;
+  if (qs) m.qs = *qs;
   m.ngroups = plan.n;
   int grid = 0;
   for (int g = 0; g < plan.n; ++g) {
     const int per_block = (plan.body[g] & 4) ? 8 : 4;  // items per block of four waves
-    grid += (ndocs[g] + per_block - 1) / per_block;
+    grid += (nq > 0 ? nq : 1) * ((ndocs[g] + per_block - 1) / per_block);
     m.end[g] = grid;
     m.off[g] = off[g];
     m.ndocs[g] = ndocs[g];

@@ -130,11 +130,40 @@ struct SinkParams {
   int* iters_out;         // per document of this query (indexed by id), or null
 };
 
-// Several length buckets of one query in one launch of one-wave items
-// (groups longest documents first; see sink_merge_kernel).
+// Several queries of one call in one Sinkhorn launch.  Every query of a call
+// sees the same documents, so queries whose launch plans are identical (same
+// kernel shape, same length buckets and row bodies) share one launch: its
+// blocks run the plan once per query of the set, each with that query's K^T
+// block, row shifts, r, v_r and output row.  The SinkParams of such a launch
+// hold the call's base pointers (column 0 / query 0).
+constexpr int kMaxLaunchQueries = 64;
+struct SinkQuerySet {
+  int nq;                       // 0: the launch runs the one query its SinkParams describe
+  int64_t U, N;                 // K^T rows per query, documents per output row
+  int4 q[kMaxLaunchQueries];    // per query: (index b in the call, first column, padded width S, 0)
+};
+
+// The parameters of query i of the set.
+__host__ __device__ inline SinkParams for_query(const SinkParams& base, const SinkQuerySet& qs, int i) {
+  SinkParams p = base;
+  const int4 q = qs.q[i];
+  p.kt = base.kt + (size_t)q.y * (size_t)qs.U;
+  p.km = base.km + (size_t)q.x * (size_t)qs.U;
+  p.r = base.r + q.y;
+  p.vr = base.vr + q.x;
+  p.out = base.out + (size_t)q.x * (size_t)qs.N;
+  if (base.iters_out) p.iters_out = base.iters_out + (size_t)q.x * (size_t)qs.N;
+  p.S = q.z;
+  return p;
+}
+
+// Several length buckets of one query (or of each query of a set) in one
+// launch of one-wave items (groups longest documents first; see
+// sink_merge_kernel).
 constexpr int kMergeMax = 8;
 struct SinkMerge {
   SinkParams p;           // drec and ndocs are replaced per group
+  SinkQuerySet qs;        // several queries: group g's blocks are nq runs of its per-query blocks
   int ngroups;
   int end[kMergeMax];     // one past the group's last block
   int off[kMergeMax];     // the group's first document record
@@ -171,10 +200,14 @@ hipError_t launch_cdist(const CdistParams& p, bool bf16, hipStream_t s, const ch
 // Row shift of the stored distances of B queries (after a launch_cdist with
 // one_query = 0): m_j = min over each query's used columns, K = exp(-lambda
 // (M - m_j)), unused columns (+inf) become 1.
-hipError_t launch_gibbs_rows(float* kt, float* km, const int2* qinfo, int64_t U, int B, float lam, hipStream_t s);
+// max_S: the widest query's padded width (sizes the grid).
+hipError_t launch_gibbs_rows(float* kt, float* km, const int2* qinfo, int64_t U, int B, int max_S, float lam,
+                             hipStream_t s);
 // whether launch_cdist can run with the selection fused in (sel_n > 0)
 bool cdist_fuses_select(const CdistParams& p, bool bf16);
-hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s);
+// grid: blocks for one query; with qs.nq > 0 the launch has nq times as many.
+hipError_t launch_sink(const SinkParams& p, const SinkConfig& cfg, int grid, hipStream_t s,
+                       const SinkQuerySet* qs = nullptr);
 hipError_t launch_nan_docs(const int* docs, int64_t ndocs, float* out, hipStream_t s);
 
 // Host-side shape choice for one (padded query width, bucket capacity, documents)
@@ -200,6 +233,6 @@ struct MergePlan {
 bool plan_merge(int S, const int* cap, const int* ndocs, int nb, MergePlan* out);
 // off / ndocs: per group, in plan order; p.drec is the start of all records.
 hipError_t launch_sink_merged(const SinkParams& p, const MergePlan& plan, const int* off, const int* ndocs,
-                              hipStream_t s, int* grid_out);
+                              hipStream_t s, int* grid_out, const SinkQuerySet* qs = nullptr);
 
 }  // namespace wmd

@@ -24,6 +24,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "device e
 CDIST = {"fp32": 0, "bf16": 1}
 SCHEDULE = {"auto": 0, "resident": 1, "per_iteration": 2, "unfused": 3}
 QUERY_GRAPH = 1
+QUERY_PER_QUERY_LAUNCHES = 2
 MAX_QUERY_LEN = 2048     # raw entries per query the library accepts
 MAX_DOC_LEN = 4096       # entries per document
 QUERY_ERRORS = {0: "ok", 1: "query word id out of range", 2: "query weight negative or not finite",
@@ -35,6 +36,8 @@ EXPORTS = [
     "wmd_get_launches", "wmd_sink_candidates", "wmd_set_sink_shape", "wmd_set_merge", "wmd_last_error",
     "wmd_query_static", "wmd_query_static_capacity",
 ]
+# include/wmd_bench.h: measurement kernels (not part of the method)
+BENCH_EXPORTS = ["wmd_bench_stream", "wmd_bench_gather", "wmd_bench_valu"]
 MERGE = {"all": 0, "none": 1}
 TUNING_FILE = os.path.join(_PKG, "tuning", "gfx950_sink_shapes.json")
 
@@ -125,6 +128,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wmd_set_merge.restype = i32
     lib.wmd_last_error.argtypes = []
     lib.wmd_last_error.restype = ctypes.c_char_p
+    lib.wmd_bench_stream.argtypes = [vp, vp, sz, i32, i32, vp, vp]
+    lib.wmd_bench_stream.restype = ctypes.c_int
+    lib.wmd_bench_gather.argtypes = [vp, i32, vp, sz, vp, i32, vp]
+    lib.wmd_bench_gather.restype = ctypes.c_int
+    lib.wmd_bench_valu.argtypes = [vp, i32, i32, i32, vp]
+    lib.wmd_bench_valu.restype = ctypes.c_int
     return lib
 
 
@@ -321,7 +330,8 @@ class Corpus:
     def query(self, batch: QueryBatch, lam: float, max_iter: int, cdist: str = "fp32",
               schedule: str = "auto", out: torch.Tensor | None = None,
               workspace: torch.Tensor | None = None, stream=None, check: bool = True,
-              tol: float = 0.0, iters: torch.Tensor | None = None, graph: bool = False) -> torch.Tensor:
+              tol: float = 0.0, iters: torch.Tensor | None = None, graph: bool = False,
+              per_query_launches: bool = False) -> torch.Tensor:
         """Distances of every query to every document: float32 [B, N] on the device.
 
         With ``check`` the call waits for the stream and raises ValueError if a
@@ -336,6 +346,9 @@ class Corpus:
         options); the device contents of the query tensors may change between
         calls.  Pass ``out`` and ``workspace`` to reuse a graph.  Needs a
         stream other than the legacy default stream.
+
+        ``per_query_launches`` gives every query its own Sinkhorn launches
+        instead of sharing launches between queries with identical plans.
         """
         B = batch.B
         if out is None:
@@ -348,7 +361,8 @@ class Corpus:
         desc = QueryDesc(B=B, q_ptr_host=batch.q_ptr_host.ctypes.data, q_ptr=_ptr(batch.q_ptr),
                          q_ids=_ptr(batch.ids), q_weights=_ptr(batch.weights), lam=float(lam),
                          max_iter=int(max_iter), cdist=CDIST[cdist], schedule=SCHEDULE[schedule],
-                         tol=float(tol), iters=_ptr(iters), flags=QUERY_GRAPH if graph else 0)
+                         tol=float(tol), iters=_ptr(iters),
+                         flags=(QUERY_GRAPH if graph else 0) | (QUERY_PER_QUERY_LAUNCHES if per_query_launches else 0))
         sh = _stream_handle(stream)
         with torch.cuda.device(self.device):
             _check(lib().wmd_query(self._h, ctypes.byref(desc), _ptr(out), _ptr(workspace),

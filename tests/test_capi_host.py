@@ -13,19 +13,30 @@ from paper_2107_06433_amd import wmd
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "wmd.h")).read()
+def header_functions(name="wmd.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(wmd_[a-z_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_function():
     lib = wmd.load_library()
-    declared = header_functions()
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert headers == ["wmd.h", "wmd_bench.h"]
+    declared = header_functions("wmd.h")
     assert declared, "no declarations parsed"
     assert sorted(wmd.EXPORTS) == declared
-    for name in declared:
+    assert sorted(wmd.BENCH_EXPORTS) == header_functions("wmd_bench.h")
+    for name in declared + wmd.BENCH_EXPORTS:
         assert hasattr(lib, name), name
+
+
+def test_measurement_kernels_reject_bad_arguments():
+    lib = wmd.load_library()
+    assert lib.wmd_bench_stream(None, None, 1024, 0, 1, None, None) == 1
+    assert lib.wmd_bench_stream(1, None, 1000, 1, 1, None, None) == 1   # copy without dst; bytes not /16
+    assert lib.wmd_bench_gather(1, 6, 1, 10, 1, 1, None) == 1          # S not a multiple of 4
+    assert lib.wmd_bench_valu(1, 1, 1, 7, None) == 1                    # unknown mode
 
 
 def test_ctypes_structs_match_header_layout():

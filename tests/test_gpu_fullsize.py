@@ -60,19 +60,24 @@ def stratified_docs(doc_ptr, per_bucket, total, seed):
 
 
 def check_launch_coverage(launches, doc_ptr, checked):
-    """Every Sinkhorn launch record names its query and, unless several
-    buckets share it (cap 0), its bucket; that query must have checked
-    documents in that bucket (in every bucket it has, for a shared launch)."""
-    bk = bucket_of(np.diff(doc_ptr))
+    """Every query has checked documents in every length bucket the corpus
+    has, so whatever (query, bucket) pairs a Sinkhorn launch runs -- one
+    query's buckets, or the same buckets of several queries that share the
+    launch -- some of its distances are checked.  Each launch record names a
+    bucket capacity (0 when several buckets share the launch) that must be one
+    of those buckets."""
+    lengths = np.diff(doc_ptr)
+    bk = bucket_of(lengths)
+    present = set(bk[lengths > 0].tolist())
+    for docs in checked:
+        assert set(bk[docs].tolist()) >= present
     names = set()
     for rec in launches:
         if not rec["name"].startswith("sink"):
             continue
         names.add(rec["name"])
-        q = rec["query"]
-        have = set(bk[checked[q]].tolist())
         if rec["cap"]:
-            assert BUCKET_CAPS.index(rec["cap"]) in have, (rec, sorted(have))
+            assert BUCKET_CAPS.index(rec["cap"]) in present, rec
     return sorted(names)
 
 
