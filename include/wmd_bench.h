@@ -30,6 +30,13 @@ extern "C" {
 int wmd_bench_stream(const void* src, void* dst, size_t bytes, int32_t copy, int32_t blocks, float* sink,
                      void* stream);
 
+/* Reads `rows` rows of row_bytes (a multiple of 64) with the cost-matrix
+ * kernel's access pattern: a wave per 16 consecutive rows, each load step
+ * reading a 64-byte piece of every one of the 16 rows (16 bytes per lane), all
+ * steps of a row in flight together.  With the compacted embedding table this
+ * is the cost matrix's HBM stream without its arithmetic. */
+int wmd_bench_tiles(const void* src, size_t rows, int32_t row_bytes, float* sink, void* stream);
+
 /* Reads row ids[k] (S floats, S a positive multiple of 4) of `table` for
  * every k < nids, in 16-byte pieces, and writes each row's sum to out[k]:
  * 4 S bytes read per id.  With the corpus's entry stream as `ids` and a table

@@ -274,8 +274,26 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   const int64_t myrow = m0 + (lane & 15);
   const bool row_ok = myrow < p.U;
-  const unsigned char* Ag = (BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32) +
-                            (size_t)(row_ok ? myrow : 0) * ROWB + 16 * (lane >> 4);
+  (void)row_ok;
+  // The wave's 16 rows are read in full 128-byte lines: per chunk of two load
+  // steps (128 bytes of every row), load j covers rows 8j .. 8j+7, 8 lanes per
+  // row, each lane 16 bytes.  (Reading the MFMA operand layout directly -- 16
+  // rows x 64 bytes per load -- touches half a line per row and load and
+  // streams at ~3.1 TB/s against ~4.7 TB/s for the same bytes read whole.)
+  // A per-wave LDS stage then hands every lane its MFMA operand: row l & 15,
+  // bytes 64 s + 16 (l >> 4) of step s, as before.
+  static_assert(CH % 2 == 0, "whole 128-byte chunks");
+  const unsigned char* Eg = BF16 ? (const unsigned char*)p.e16 : (const unsigned char*)p.e32;
+  const unsigned char* Ag0;
+  const unsigned char* Ag1;
+  {
+    const int64_t r0 = m0 + (lane >> 3), r1 = m0 + 8 + (lane >> 3);  // rows past U read row 0
+    Ag0 = Eg + (size_t)(r0 < p.U ? r0 : 0) * ROWB + 16 * (lane & 7);
+    Ag1 = Eg + (size_t)(r1 < p.U ? r1 : 0) * ROWB + 16 * (lane & 7);
+  }
+  constexpr int STR = 144;  // stage row pitch in bytes: 128 + 16 (rows fall on distinct banks)
+  __shared__ __attribute__((aligned(16))) unsigned char stage[4][16 * STR];
+  unsigned char* st = stage[wave];
   f32x4 acc[NT > 0 ? NT : 1], acc4[N4 > 0 ? N4 : 1];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -299,7 +317,10 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
   int used_r[4];
   auto load_rows = [&]() {
 #pragma unroll
-    for (int i = 0; i < CH; ++i) buf[i] = *(const uint4*)(Ag + (size_t)i * 64);
+    for (int c = 0; c < CH / 2; ++c) {
+      buf[2 * c] = *(const uint4*)(Ag0 + (size_t)c * 128);
+      buf[2 * c + 1] = *(const uint4*)(Ag1 + (size_t)c * 128);
+    }
     // the epilogue's per-row and per-column data, fetched early for the same
     // reason (indices clamped)
 #pragma unroll
@@ -485,17 +506,33 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
     __syncthreads();
   }
   {
+    uint4 op = make_uint4(0, 0, 0, 0);  // this lane's operand of the current step
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
+      if (i % 2 == 0) {
+        // stage chunk i / 2 (rows 8j + (l >> 3), bytes 16 (l & 7)) and read
+        // this lane's operands of steps i and i + 1 back
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        *(uint4*)(st + (lane >> 3) * STR + 16 * (lane & 7)) = buf[i];
+        *(uint4*)(st + (8 + (lane >> 3)) * STR + 16 * (lane & 7)) = buf[i + 1];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        op = *(const uint4*)(st + (lane & 15) * STR + 16 * (lane >> 4));
+        buf[i + 1] = *(const uint4*)(st + (lane & 15) * STR + 64 + 16 * (lane >> 4));
+      } else {
+        op = buf[i];
+      }
       const int kb = i * 64 + 16 * (lane >> 4);  // byte offset of this lane's k run
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const uint4 q = *(const uint4*)(smem + (t * 16 + (lane & 15)) * LDQ + kb);
         if constexpr (BF16) {
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, buf[i]),
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, op),
                                                           __builtin_bit_cast(bf16x8, q), acc[t], 0, 0, 0);
         } else {
-          const f32x4 a = __builtin_bit_cast(f32x4, buf[i]);
+          const f32x4 a = __builtin_bit_cast(f32x4, op);
           const f32x4 b = __builtin_bit_cast(f32x4, q);
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[t], 0, 0, 0);
@@ -505,7 +542,7 @@ __global__ void __launch_bounds__(256) cdist_skinny_kernel(CdistParams p) {
 #pragma unroll
         for (int u = 0; u < N4; ++u) {
           const uint4 q = *(const uint4*)(smem + (NT * 16 + 4 * u + (lane & 3)) * LDQ + kb);
-          const f32x4 a = __builtin_bit_cast(f32x4, buf[i]);
+          const f32x4 a = __builtin_bit_cast(f32x4, op);
           const f32x4 b = __builtin_bit_cast(f32x4, q);
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc4[u] = __builtin_amdgcn_mfma_f32_4x4x1f32(a[j], b[j], acc4[u], 0, 0, 0);
@@ -682,9 +719,10 @@ bool skinny_steps_ok(int dp, bool bf16) {
 
 }  // namespace
 
-// the skinny kernel whenever its Q tile (at most 32 rows) fits in 64 KiB of LDS
+// the skinny kernel whenever its Q tile (at most 32 rows), the row stages
+// (9 KiB) and the selection's arrays (under 2 KiB) fit in 64 KiB of LDS
 static bool skinny_fits(const CdistParams& p, bool bf16) {
-  return skinny_steps_ok(p.dp, bf16) && skinny_lds(2, 0, p.dp, bf16) <= 65536 && p.C <= 32;
+  return skinny_steps_ok(p.dp, bf16) && skinny_lds(2, 0, p.dp, bf16) + 9216 + 2048 <= 65536 && p.C <= 32;
 }
 
 bool cdist_fuses_select(const CdistParams& p, bool bf16) { return p.U > 0 && p.C > 0 && skinny_fits(p, bf16); }

@@ -46,6 +46,34 @@ __global__ void __launch_bounds__(256) stream_kernel(const float4* __restrict__ 
   if (!copy && acc == -1.2345678e30f) *sink = acc;
 }
 
+// Row tiles: the cost-matrix kernel's read pattern.  Rows of row_bytes
+// (a multiple of 64); each wave owns 16 consecutive rows and, per step, lane l
+// reads bytes [64 i + 16 (l >> 4), +16) of row l & 15, all steps of the row
+// issued at once; one wave per 16 rows, blocks of four waves.
+__global__ void __launch_bounds__(256) tile_kernel(const unsigned char* __restrict__ src, size_t rows, int row_bytes,
+                                                  float* sink) {
+  const int lane = threadIdx.x & 63;
+  const size_t r0 = ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (r0 >= rows) return;
+  const size_t row = r0 + (lane & 15) < rows ? r0 + (lane & 15) : rows - 1;
+  const unsigned char* base = src + row * (size_t)row_bytes + 16 * (lane >> 4);
+  const int steps = row_bytes / 64;
+  float acc = 0.f;
+  int i = 0;
+  for (; i + 8 <= steps; i += 8) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *(const float4*)(base + (size_t)(i + u) * 64);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u].x + v[u].w;
+  }
+  for (; i < steps; ++i) {
+    const float4 v = *(const float4*)(base + (size_t)i * 64);
+    acc += v.x + v.w;
+  }
+  if (acc == -1.2345678e30f) *sink = acc;
+}
+
 // Gather: a row of S floats per id, L = S/4 lanes per row (a power of two up
 // to 64; wider rows loop), 64 / L rows per wave, consecutive ids to
 // consecutive row groups, grid-stride.  Each row's values are summed and one
@@ -113,6 +141,14 @@ int wmd_bench_stream(const void* src, void* dst, size_t bytes, int32_t copy, int
   if (!src || (copy && !dst) || (!copy && !sink) || bytes % 16 || blocks < 1) return 1;
   stream_kernel<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
       static_cast<const float4*>(src), static_cast<float4*>(dst), bytes / 16, copy, sink);
+  return hipGetLastError() == hipSuccess ? 0 : 3;
+}
+
+int wmd_bench_tiles(const void* src, size_t rows, int32_t row_bytes, float* sink, void* stream) {
+  if (!src || !sink || rows < 1 || row_bytes < 64 || row_bytes % 64) return 1;
+  const size_t blocks = (rows + 63) / 64;
+  tile_kernel<<<(unsigned)blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
+      static_cast<const unsigned char*>(src), rows, row_bytes, sink);
   return hipGetLastError() == hipSuccess ? 0 : 3;
 }
 

@@ -60,6 +60,22 @@ def hbm(nbytes: int = 2 << 30, reps: int = 5) -> dict:
     return {"read_GBps": best["read"], "copy_GBps": best["copy"], "bytes": nbytes}
 
 
+def tiles(rows: int, row_bytes: int, reps: int = 10) -> dict:
+    """The cost-matrix kernel's read pattern over rows x row_bytes (16-row
+    tiles, 64-byte pieces) next to a plain stream of the same bytes."""
+    lib = wmd.lib()
+    nbytes = rows * row_bytes
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sh = torch.cuda.current_stream().cuda_stream
+    t_tile = _time(lambda: _ok(lib.wmd_bench_tiles(src.data_ptr(), rows, row_bytes, sink.data_ptr(), sh)), reps)
+    t_stream = min(_time(lambda: _ok(lib.wmd_bench_stream(src.data_ptr(), None, nbytes, 0, b, sink.data_ptr(), sh)),
+                         reps) for b in (673, 2048, 8192))
+    return {"rows": rows, "row_bytes": row_bytes, "bytes": nbytes, "tile_us": t_tile * 1e3,
+            "tile_GBps": nbytes / (t_tile * 1e-3) / 1e9, "stream_us": t_stream * 1e3,
+            "stream_GBps": nbytes / (t_stream * 1e-3) / 1e9}
+
+
 def gather(ids: torch.Tensor, U: int, S: int, reps: int = 10) -> dict:
     """Rows of S floats from a U-row table, in the order of `ids` (device int32)."""
     lib = wmd.lib()
@@ -93,6 +109,7 @@ def measure(ids: torch.Tensor | None = None, U: int = 0, S: int = 20) -> dict:
     r = {"hbm": hbm(), "valu": valu()}
     if ids is not None and U > 0:
         r["gather"] = gather(ids, U, S)
+        r["cost_matrix_stream"] = tiles(U, 1280)  # the compacted f32 table, d = 300 padded to 320
     return r
 
 

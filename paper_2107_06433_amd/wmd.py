@@ -37,7 +37,7 @@ EXPORTS = [
     "wmd_query_static", "wmd_query_static_capacity",
 ]
 # include/wmd_bench.h: measurement kernels (not part of the method)
-BENCH_EXPORTS = ["wmd_bench_stream", "wmd_bench_gather", "wmd_bench_valu"]
+BENCH_EXPORTS = ["wmd_bench_stream", "wmd_bench_tiles", "wmd_bench_gather", "wmd_bench_valu"]
 MERGE = {"all": 0, "none": 1}
 TUNING_FILE = os.path.join(_PKG, "tuning", "gfx950_sink_shapes.json")
 
@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wmd_last_error.restype = ctypes.c_char_p
     lib.wmd_bench_stream.argtypes = [vp, vp, sz, i32, i32, vp, vp]
     lib.wmd_bench_stream.restype = ctypes.c_int
+    lib.wmd_bench_tiles.argtypes = [vp, sz, i32, vp, vp]
+    lib.wmd_bench_tiles.restype = ctypes.c_int
     lib.wmd_bench_gather.argtypes = [vp, i32, vp, sz, vp, i32, vp]
     lib.wmd_bench_gather.restype = ctypes.c_int
     lib.wmd_bench_valu.argtypes = [vp, i32, i32, i32, vp]
