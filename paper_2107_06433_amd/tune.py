@@ -78,8 +78,10 @@ def tune_workload(name: str, cdist: str = "fp32", reps: int = 2, max_candidates:
         singles = [batch]
     out = torch.empty((max(sb.B for sb in singles), c.N), dtype=torch.float32, device="cuda")
     ws = torch.empty(max(corpus.workspace_bytes(sb) for sb in singles), dtype=torch.uint8, device="cuda")
+    # every query keeps launches of its own (queries sharing a launch would
+    # blur which (S, cap) pair a launch time belongs to)
     for sb in singles:  # warm caches and code
-        corpus.query(sb, w.lam, w.max_iter, cdist=cdist, out=out, workspace=ws)
+        corpus.query(sb, w.lam, w.max_iter, cdist=cdist, out=out, workspace=ws, per_query_launches=True)
     times = defaultdict(lambda: defaultdict(float))
     t0 = time.time()
     for r in range(R):
@@ -88,7 +90,8 @@ def tune_workload(name: str, cdist: str = "fp32", reps: int = 2, max_candidates:
         for _ in range(reps):
             corpus.set_timing(True)
             for sb in singles:
-                corpus.query(sb, w.lam, w.max_iter, cdist=cdist, out=out, workspace=ws, check=False)
+                corpus.query(sb, w.lam, w.max_iter, cdist=cdist, out=out, workspace=ws, check=False,
+                             per_query_launches=True)
             torch.cuda.synchronize()
             recs = corpus.launches()
             corpus.set_timing(False)
@@ -116,13 +119,15 @@ def main():
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--max-queries", type=int, default=128)
     ap.add_argument("--per-query", action="store_true", help="time one query per call")
+    ap.add_argument("--cdist", default="fp32", choices=["fp32", "bf16"])
     args = ap.parse_args()
     table = {"arch": "gfx950", "entries": []}
     if os.path.exists(args.out):
         with open(args.out) as f:
             table = json.load(f)
     for name in args.workloads:
-        new = tune_workload(name, reps=args.reps, max_queries=args.max_queries, per_query=args.per_query)
+        new = tune_workload(name, cdist=args.cdist, reps=args.reps, max_queries=args.max_queries,
+                            per_query=args.per_query)
         keys = {(e["S"], e["cap"], e["ndocs_log2"]) for e in new}
         table["entries"] = [e for e in table["entries"] if (e["S"], e["cap"], e["ndocs_log2"]) not in keys] + new
         gain = sum(e["model_choice_us"] for e in new) / max(1e-9, sum(e["us"] for e in new))
