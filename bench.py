@@ -280,7 +280,7 @@ def batched_leg() -> dict:
     return res
 
 
-def serving_leg(rates=(2000.0, 1500.0, 1000.0), measured=4000, warm=500) -> dict:
+def serving_leg(rates=(2000.0, 1500.0, 1250.0, 1000.0), measured=4000, warm=500) -> dict:
     """A short open-loop serving trace on the full serving corpus (Poisson
     arrivals, continuous batching on three streams, bf16 cost matrix): p50/p99
     at 2,000 queries/s and at lower rates; the highest rate served within 3%."""
