@@ -30,18 +30,22 @@ extern "C" {
 int wmd_bench_stream(const void* src, void* dst, size_t bytes, int32_t copy, int32_t blocks, float* sink,
                      void* stream);
 
-/* Reads `rows` rows of row_bytes (a multiple of 64) with the cost-matrix
- * kernel's access pattern: a wave per 16 consecutive rows, each load step
- * reading a 64-byte piece of every one of the 16 rows (16 bytes per lane), all
- * steps of a row in flight together.  With the compacted embedding table this
- * is the cost matrix's HBM stream without its arithmetic. */
+/* Reads `rows` rows of row_bytes (a multiple of 64) in MFMA operand order: a
+ * wave per 16 consecutive rows, each load step reading a 64-byte piece of
+ * every one of the 16 rows (16 bytes per lane, each load instruction touching
+ * 16 lines), all steps of a row in flight together.  Set beside a plain
+ * stream of the same bytes it prices that read order, which the cost-matrix
+ * kernel avoids by reading whole 128-byte lines and re-laying them out in
+ * LDS. */
 int wmd_bench_tiles(const void* src, size_t rows, int32_t row_bytes, float* sink, void* stream);
 
-/* Reads row ids[k] (S floats, S a positive multiple of 4) of `table` for
- * every k < nids, in 16-byte pieces, and writes each row's sum to out[k]:
- * 4 S bytes read per id.  With the corpus's entry stream as `ids` and a table
- * of the K^T shape (U rows of S floats) this is the Sinkhorn row gather on
- * its own. */
+/* Reads row ids[k] (S floats, S a multiple of 4 from 4 to 512) of `table`
+ * for every k < nids and writes each row's sum to out[k]: 4 S bytes read per
+ * id.  Rows are read as the Sinkhorn kernels read their K^T rows: 16-byte
+ * pieces, two per lane, eight rows per lane with all their loads in flight
+ * together.  Every ids[k] must name a row of `table`.  With the corpus's
+ * entry stream as `ids` and a table of the K^T shape (U rows of S floats)
+ * this is the Sinkhorn row gather on its own. */
 int wmd_bench_gather(const float* table, int32_t S, const int32_t* ids, size_t nids, float* out, int32_t blocks,
                      void* stream);
 

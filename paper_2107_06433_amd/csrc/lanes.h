@@ -12,6 +12,7 @@ namespace wmd {
 enum : int {
   kDppXor1 = 0xB1,        // quad_perm [1,0,3,2]
   kDppXor2 = 0x4E,        // quad_perm [2,3,0,1]
+  kDppXor3 = 0x1B,        // quad_perm [3,2,1,0]
   kDppRor4 = 0x124,       // row_ror:4
   kDppRor8 = 0x128,       // row_ror:8
   kDppMirror = 0x140,     // row_mirror      (lane l <- 15-l)

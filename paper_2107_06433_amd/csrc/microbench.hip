@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(256) stream_kernel(const float4* __restrict__ 
   if (!copy && acc == -1.2345678e30f) *sink = acc;
 }
 
-// Row tiles: the cost-matrix kernel's read pattern.  Rows of row_bytes
+// Row tiles in MFMA operand order (each lane loading its own operand pieces).  Rows of row_bytes
 // (a multiple of 64); each wave owns 16 consecutive rows and, per step, lane l
 // reads bytes [64 i + 16 (l >> 4), +16) of row l & 15, all steps of the row
 // issued at once; one wave per 16 rows, blocks of four waves.
@@ -74,31 +74,50 @@ __global__ void __launch_bounds__(256) tile_kernel(const unsigned char* __restri
   if (acc == -1.2345678e30f) *sink = acc;
 }
 
-// Gather: a row of S floats per id, L = S/4 lanes per row (a power of two up
-// to 64; wider rows loop), 64 / L rows per wave, consecutive ids to
-// consecutive row groups, grid-stride.  Each row's values are summed and one
-// float per row is written (4 bytes against the 4 S read).
+// Gather, issued the way the Sinkhorn kernels gather their K^T rows: L =
+// 2^l lanes per row, each reading two 16-byte pieces (pieces past the row
+// are skipped), 64 / L rows per wave and load step, and eight such steps per
+// pass, every load of a pass in flight before any value is used.  Each row's
+// values are summed and one float per row is written (4 bytes against the
+// 4 S read).  ids are read with clamped indices, so every read stays inside
+// ids[0 .. nids) and the rows they name.
 __global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ table, int S,
                                                     const int* __restrict__ ids, size_t nids, float* __restrict__ out) {
+  constexpr int T = 8;  // load steps per pass
   const int n4 = S >> 2;
   int lg = 0;
-  while ((1 << lg) < n4 && lg < 6) ++lg;
+  while ((2 << lg) < n4) ++lg;
   const int L = 1 << lg, R = 64 >> lg;
   const int lane = threadIdx.x & 63;
   const int sub = lane & (L - 1), rw = lane >> lg;
   const size_t waves = (size_t)gridDim.x * (blockDim.x >> 6);
-  for (size_t g = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g * R < nids; g += waves) {
-    const size_t k = g * R + rw;
-    const bool ok = k < nids;
-    const int id = ids[ok ? k : 0];
-    const float4* row = (const float4*)(table + (size_t)id * S);
-    float acc = 0.f;
-    for (int c = sub; c < n4; c += L) {
-      const float4 v = row[c];
-      acc += (v.x + v.y) + (v.z + v.w);
+  const size_t per = (size_t)R * T;
+  for (size_t g = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g * per < nids; g += waves) {
+    int id[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const size_t k = g * per + rw + (size_t)R * t;
+      id[t] = ids[k < nids ? k : nids - 1];
     }
-    for (int o = 1; o < L; o <<= 1) acc += __shfl_xor(acc, o);
-    if (ok && sub == 0) out[k] = acc;
+    float4 v[T][2];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float4* row = (const float4*)(table + (size_t)id[t] * S);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int c = sub + L * i;
+        v[t][i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < n4) v[t][i] = row[c];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      float acc = (v[t][0].x + v[t][0].y) + (v[t][0].z + v[t][0].w) + (v[t][1].x + v[t][1].y) +
+                  (v[t][1].z + v[t][1].w);
+      for (int o = 1; o < L; o <<= 1) acc += __shfl_xor(acc, o);
+      const size_t k = g * per + rw + (size_t)R * t;
+      if (k < nids && sub == 0) out[k] = acc;
+    }
   }
 }
 
@@ -154,7 +173,7 @@ int wmd_bench_tiles(const void* src, size_t rows, int32_t row_bytes, float* sink
 
 int wmd_bench_gather(const float* table, int32_t S, const int32_t* ids, size_t nids, float* out, int32_t blocks,
                      void* stream) {
-  if (!table || !ids || !out || S < 4 || S % 4 || blocks < 1) return 1;
+  if (!table || !ids || !out || S < 4 || S > 512 || S % 4 || blocks < 1) return 1;
   gather_kernel<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(table, S, ids, nids, out);
   return hipGetLastError() == hipSuccess ? 0 : 3;
 }

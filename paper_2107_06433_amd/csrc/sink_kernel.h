@@ -185,9 +185,21 @@ __device__ __forceinline__ void high_div(const float (&np)[HighPack<M, N>::P], c
 // The same idea inside a lane quad, with DPP: x[e] / (sum over lane bit 0
 // (L = 1) or bits 0 and 1 (L = 2) of den[e]), optionally also summed over
 // lane bits 2 and 3 (HI23) and then over bit 4 (HB >= 1) and bit 5 (HB = 2)
-// with permlane swaps.  Lane q of a quad ends up with the total of element
-// 4i + q (or 2i + (q & 1)), divides once, and quad broadcasts give every lane
-// all the quotients.
+// with permlane swaps.  The rows come in groups of four (L = 2), then pairs,
+// then a last single row; quad lane q ends up with the total of row a + q of
+// a group (a + (q & 1) of a pair), divides once, and quad permutations give
+// every lane all the quotients.
+//
+// Two forms.  In natural slots (PERM false) every lane holds row t in slot
+// t, and each reduce-scatter step picks which element to keep and which to
+// hand over with two selects.  With permuted slots (PERM) slot a + s of quad
+// lane q holds row a + (s ^ q) of a group of four, row a + (s ^ (q & 1)) of a
+// pair (row_slot): then for every lane the bit-0 step is its slot a plus its
+// partner's slot a + 1 (and slots a + 2, a + 3 alike), the bit-1 step its
+// first partial plus its bit-1 partner's second, one DPP add each and no
+// selects; the row a lane keeps is the row in its slot a, so its numerator
+// is slot a of x, and slot a of the quotients needs no move.  Both forms add
+// the same two operands at every step.
 template <int L, int N>
 struct LowPack {
   static constexpr int NQ = L == 2 ? N / 4 : 0;
@@ -196,27 +208,38 @@ struct LowPack {
   static constexpr int P = NQ + NP + N1;
 };
 
+// Register slot t of quad lane q holds row row_slot(t) of the lane's rows
+// (a permutation inside each group; q = lane & 3, or lane & 1 for L = 1).
 template <int L, int N>
+__device__ __forceinline__ int row_slot(int t, int q) {
+  using H = LowPack<L, N>;
+  return t < 4 * H::NQ ? t ^ q : t < 4 * H::NQ + 2 * H::NP ? t ^ (q & 1) : t;
+}
+
+// The numerators of the rows whose totals this lane will hold.
+template <int L, int N, bool PERM>
 __device__ __forceinline__ void pack_low(const float (&x)[N], float (&xp)[LowPack<L, N>::P], int lane) {
   using H = LowPack<L, N>;
   const int q = lane & 3;
 #pragma unroll
   for (int i = 0; i < H::NQ; ++i)
-    xp[i] = pick(q & 2, pick(q & 1, x[4 * i], x[4 * i + 1]), pick(q & 1, x[4 * i + 2], x[4 * i + 3]));
+    xp[i] = PERM ? x[4 * i]
+                 : pick(q & 2, pick(q & 1, x[4 * i], x[4 * i + 1]), pick(q & 1, x[4 * i + 2], x[4 * i + 3]));
 #pragma unroll
   for (int i = 0; i < H::NP; ++i) {
     const int a = 4 * H::NQ + 2 * i;
-    xp[H::NQ + i] = pick(q & 1, x[a], x[a + 1]);
+    xp[H::NQ + i] = PERM ? x[a] : pick(q & 1, x[a], x[a + 1]);
   }
   if constexpr (H::N1 > 0) xp[H::NQ + H::NP] = x[N - 1];
 }
 
-template <int L, bool HI23, int HB, int N>
+template <int L, bool HI23, int HB, int N, bool PERM>
 __device__ __forceinline__ void low_div(const float (&np)[LowPack<L, N>::P], const float (&den)[N], float (&out)[N],
                                         int lane) {
   using H = LowPack<L, N>;
   const bool b0 = lane & 1, b1 = lane & 2;
-  // lane parity b0 keeps element (b0 ? b : a) and hands its partner the other
+  // natural slots: lane parity b0 keeps element (b0 ? b : a) and hands its
+  // partner the other
   auto pair0 = [&](float a, float b) {
     // opaque copies: a select between two elements of one register array can
     // become a load at a lane-dependent index (see pick)
@@ -235,22 +258,37 @@ __device__ __forceinline__ void low_div(const float (&np)[LowPack<L, N>::P], con
 #pragma unroll
   for (int i = 0; i < H::NQ; ++i) {
     const int a = 4 * i;
-    const float pab = pair0(den[a], den[a + 1]), pcd = pair0(den[a + 2], den[a + 3]);
-    const float z = hi23((b1 ? pcd : pab) + dpp<kDppXor2>(b1 ? pab : pcd));
-    const float v = fast_div(np[i], z);
-    out[a] = dpp<0x00>(v);      // quad_perm [0,0,0,0]
-    out[a + 1] = dpp<0x55>(v);  // quad_perm [1,1,1,1]
-    out[a + 2] = dpp<0xAA>(v);  // quad_perm [2,2,2,2]
-    out[a + 3] = dpp<0xFF>(v);  // quad_perm [3,3,3,3]
+    if constexpr (PERM) {
+      const float z0 = den[a] + dpp<kDppXor1>(den[a + 1]);
+      const float z2 = den[a + 2] + dpp<kDppXor1>(den[a + 3]);
+      const float v = fast_div(np[i], hi23(z0 + dpp<kDppXor2>(z2)));
+      out[a] = v;
+      out[a + 1] = dpp<kDppXor1>(v);
+      out[a + 2] = dpp<kDppXor2>(v);
+      out[a + 3] = dpp<kDppXor3>(v);
+    } else {
+      const float pab = pair0(den[a], den[a + 1]), pcd = pair0(den[a + 2], den[a + 3]);
+      const float z = hi23((b1 ? pcd : pab) + dpp<kDppXor2>(b1 ? pab : pcd));
+      const float v = fast_div(np[i], z);
+      out[a] = dpp<0x00>(v);      // quad_perm [0,0,0,0]
+      out[a + 1] = dpp<0x55>(v);  // quad_perm [1,1,1,1]
+      out[a + 2] = dpp<0xAA>(v);  // quad_perm [2,2,2,2]
+      out[a + 3] = dpp<0xFF>(v);  // quad_perm [3,3,3,3]
+    }
   }
 #pragma unroll
   for (int i = 0; i < H::NP; ++i) {
     const int a = 4 * H::NQ + 2 * i;
-    float z = pair0(den[a], den[a + 1]);
+    float z = PERM ? den[a] + dpp<kDppXor1>(den[a + 1]) : pair0(den[a], den[a + 1]);
     if constexpr (L == 2) z += dpp<kDppXor2>(z);
     const float v = fast_div(np[H::NQ + i], hi23(z));
-    out[a] = dpp<0xA0>(v);      // quad_perm [0,0,2,2]
-    out[a + 1] = dpp<0xF5>(v);  // quad_perm [1,1,3,3]
+    if constexpr (PERM) {
+      out[a] = v;
+      out[a + 1] = dpp<kDppXor1>(v);
+    } else {
+      out[a] = dpp<0xA0>(v);      // quad_perm [0,0,2,2]
+      out[a + 1] = dpp<0xF5>(v);  // quad_perm [1,1,3,3]
+    }
   }
   if constexpr (H::N1 > 0) {
     float z = den[N - 1];
@@ -327,6 +365,23 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
   const int S = p.S;
   const int vr = *p.vr;
   float* rvs = lds + 2 * nwaves * cw_stride + 2 * cw_stride;  // multi-wave items only
+  // Row sums over 2, 4, 16, 32 or 64 column lanes divide packed within
+  // quads (lane bits 0 and 1), the quads' totals summed over the remaining
+  // column-lane bits first; 8 column lanes (lg_cg 3) sum each row plainly.
+  // One-wave items of at most 40 cells with 2 or 4 column lanes keep their
+  // rows in permuted register slots (PERM, see low_div): once the rows are
+  // gathered, slot t of this lane holds row slot_row(t) of its row lane, and
+  // the w loads and stores of the other schedules follow it.  The
+  // permutation is a few exec-masked swaps per item against two selects per
+  // reduce-scatter step in every iteration.  Elsewhere the swaps cost more
+  // registers than they save: larger blocks, wider column groups and
+  // multi-wave items lose a wave per SIMD with them (compiled register
+  // counts), which costs the batched workloads more than the selects.
+  constexpr bool ROWQ = LG_CG != 0 && LG_CG != 3;
+  constexpr int LQ = LG_CG == 1 ? 1 : 2;
+  constexpr bool PERM = ROWQ && !MW && LG_CG <= 2 && TR * TC <= 40;
+  const int qid = lane & (LQ == 1 ? 1 : 3);
+  auto slot_row = [&](int t) { return PERM ? row_slot<LQ, TR>(t, qid) : t; };
 
   for (int base = blk * items; base < p.ndocs; base += nblk * items) {
     const int item = base + slot;
@@ -424,6 +479,43 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     // (this keeps the compiler from carrying the loaded values, or the row
     // ids, into the iterations)
     asm volatile("" : "+v"(cm));
+    // The rows were read in their natural slots (the lanes of a quad reading
+    // the same K^T row, so that a load touches a row's lines once); PERM
+    // wants them in slot_row order.  Swapping slot pairs by lane bit 0 and
+    // then slot pairs two apart by lane bit 1 takes slot t to row t ^ q in
+    // groups of four and t ^ (q & 1) in pairs.
+    if constexpr (PERM) {
+      using LP = LowPack<LQ, TR>;
+      constexpr int G4 = 4 * LP::NQ, G2 = G4 + 2 * LP::NP;
+      // swaps in the lanes whose bit is set only (exec-masked moves, no
+      // selects and no second copy of the block)
+      auto swap = [](auto& a, auto& b) {
+        const auto t = a;
+        a = b;
+        b = t;
+      };
+      if (qid & 1) {
+#pragma unroll
+        for (int t = 0; t < G2; t += 2) {
+#pragma unroll
+          for (int e = 0; e < TC; ++e) swap(K[t][e], K[t + 1][e]);
+          swap(cw[t], cw[t + 1]);
+          swap(wid[t], wid[t + 1]);
+        }
+      }
+      if (qid & 2) {
+#pragma unroll
+        for (int t = 0; t < G4; t += 4) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int e = 0; e < TC; ++e) swap(K[t + h][e], K[t + h + 2][e]);
+            swap(cw[t + h], cw[t + h + 2]);
+            swap(wid[t + h], wid[t + h + 2]);
+          }
+        }
+      }
+    }
     float rv[TC], u[TC];
 #pragma unroll
     for (int e = 0; e < TC; ++e) {
@@ -449,19 +541,14 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     constexpr int MC = HALF ? 1 : LG_CG <= 4 ? 3 : 2;  // half-wave items: bit 4 only
     float rpk[HighPack<MC, TC>::P];
     if constexpr (COLP) pack_high<MC, TC>(rv, rpk, lane);
-    // Row sums over 2, 4, 16, 32 or 64 column lanes divide packed within
-    // quads (lane bits 0 and 1), the quads' totals summed over the remaining
-    // column-lane bits first; 8 column lanes (lg_cg 3) sum each row plainly.
-    constexpr bool ROWQ = LG_CG != 0 && LG_CG != 3;
-    constexpr int LQ = LG_CG == 1 ? 1 : 2;
     constexpr int RHB = LG_CG > 4 ? LG_CG - 4 : 0;
     float cqk[LowPack<LQ, TR>::P];
-    if constexpr (ROWQ) pack_low<LQ, TR>(cw, cqk, lane);
+    if constexpr (ROWQ) pack_low<LQ, TR, PERM>(cw, cqk, lane);
     // w_j = c_j / s_j for this lane's rows, from partial dot products s
     // (summed over the column lanes here), in every column lane of the row
     auto row_div = [&](float (&sp)[TR], float (&q)[TR]) {
       if constexpr (ROWQ) {
-        low_div<LQ, (LG_CG >= 4), RHB>(cqk, sp, q, lane);
+        low_div<LQ, (LG_CG >= 4), RHB, TR, PERM>(cqk, sp, q, lane);
       } else {
         sum_low<LG_CG>(sp);
 #pragma unroll
@@ -472,7 +559,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
     if (load_w) {
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
-        const int j = rs + RS * t;
+        const int j = rs + RS * slot_row(t);
         wv[t] = (j < n && wid[t] >= 0) ? p.w[beg + j] : 0.f;
       }
     }
@@ -495,7 +582,7 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
           if (cg == 0 && active) {
 #pragma unroll
             for (int t = 0; t < TR; ++t) {
-              const int j = rs + RS * t;
+              const int j = rs + RS * slot_row(t);
               if (j < n) p.w[beg + j] = wv[t];
             }
           }
@@ -575,9 +662,12 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
             }
           }
           __syncthreads();
-          // the column thread adds the waves' partials (all loads in flight
-          // together) and divides: r over the total, once per column instead
-          // of in every lane
+          // the column thread adds the waves' partials in wave order and
+          // divides: r over the total, once per column instead of in every
+          // lane.  (The guarded adds compile to one LDS round trip per wave;
+          // loading every wave's partial first measured no faster at the
+          // batched workload, whose waves keep the SIMDs busy meanwhile, and
+          // costs 16-wave blocks a wave per SIMD in registers.)
           for (int c = threadIdx.x; c < cw_stride; c += blockDim.x) {
             float a = 0.f;
 #pragma unroll

@@ -76,9 +76,14 @@ def tiles(rows: int, row_bytes: int, reps: int = 10) -> dict:
             "stream_GBps": nbytes / (t_stream * 1e-3) / 1e9}
 
 
-def gather(ids: torch.Tensor, U: int, S: int, reps: int = 10) -> dict:
-    """Rows of S floats from a U-row table, in the order of `ids` (device int32)."""
+def gather(ids: torch.Tensor, U: int, S: int, reps: int = 10, min_rows: int = 1 << 22) -> dict:
+    """Rows of S floats from a U-row table, in the order of `ids` (device
+    int32), the id stream repeated to at least min_rows rows: a single pass
+    over one corpus's entries (tens of MB) is over in a few microseconds, and
+    its time would be mostly the launch's own."""
     lib = wmd.lib()
+    if ids.numel() < min_rows:
+        ids = ids.repeat(-(-min_rows // ids.numel()))
     table = torch.rand(U * S, dtype=torch.float32, device="cuda")
     out = torch.empty(ids.numel(), dtype=torch.float32, device="cuda")
     sh = torch.cuda.current_stream().cuda_stream

@@ -36,6 +36,7 @@ def test_measurement_kernels_reject_bad_arguments():
     assert lib.wmd_bench_stream(None, None, 1024, 0, 1, None, None) == 1
     assert lib.wmd_bench_stream(1, None, 1000, 1, 1, None, None) == 1   # copy without dst; bytes not /16
     assert lib.wmd_bench_gather(1, 6, 1, 10, 1, 1, None) == 1          # S not a multiple of 4
+    assert lib.wmd_bench_gather(1, 516, 1, 10, 1, 1, None) == 1        # S past 512
     assert lib.wmd_bench_valu(1, 1, 1, 7, None) == 1                    # unknown mode
     assert lib.wmd_bench_tiles(1, 10, 100, 1, None) == 1                 # row bytes not a multiple of 64
 
