@@ -597,7 +597,16 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         for (int t = 0; t < TR; ++t) a = fmaf(K[t][e], wv[t], a);
         acc[e] = a;
       }
-      float un[TC];
+      // The new column scalings go straight into u (nothing below reads the
+      // old u but the tolerance test, which keeps its own copy): a separate
+      // array would cost a move per column and iteration to carry it back.
+      const bool chk = p.tol > 0.f;
+      float uprev[TC];
+      if (chk) {
+#pragma unroll
+        for (int e = 0; e < TC; ++e) uprev[e] = u[e];
+      }
+      float (&un)[TC] = u;
       if constexpr (COLP) {
         high_div<MC, TC, LG_CG>(rpk, acc, un);
       } else {
@@ -683,18 +692,15 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
           for (int e = 0; e < TC; ++e) un[e] = fast_div(rv[e], acc[e]);
         }
       }
-      if (p.tol > 0.f) {
+      if (chk) {
         // x = 1/u, so the relative change |x_new - x| / x_new is
         // |u - u_new| / u; padding columns (u = 0) are skipped.  Every lane of
         // the item holds the same u, so the decision is uniform over the
         // item's waves.
         float dm = 0.f;
-        float uprev[TC];
 #pragma unroll
         for (int e = 0; e < TC; ++e) {
-          if (u[e] > 0.f) dm = fmaxf(dm, fabsf(u[e] - un[e]) * __builtin_amdgcn_rcpf(u[e]));
-          uprev[e] = u[e];
-          u[e] = un[e];
+          if (uprev[e] > 0.f) dm = fmaxf(dm, fabsf(uprev[e] - u[e]) * __builtin_amdgcn_rcpf(uprev[e]));
         }
         dm = max_low<LG_CG>(dm);
         if constexpr (HALF) {
@@ -721,8 +727,6 @@ __device__ __forceinline__ void sink_body(const SinkParams& p, int blk, int nblk
         }
         continue;
       }
-#pragma unroll
-      for (int e = 0; e < TC; ++e) u[e] = un[e];
     }
 
     if (store_u && rs == 0 && active) {
