@@ -532,3 +532,41 @@ def test_tolerance_stop_counts_and_values(W, single, tol):
         sel = docs[kd == kk]
         ref = oracle_support(c, ids, qw, single.lam, int(kk), sel)
         assert_close(got[sel], ref, TOL32, f"tol={tol} k={kk}")
+
+
+@pytest.mark.parametrize("vr", [7, 12, 20])
+def test_permuted_slot_shapes_every_schedule(W, vr):
+    """One-wave shapes with 2 or 4 column lanes hold the rows of their small
+    bodies (at most 40 cells per lane) in permuted register slots.  Each such
+    shape, pinned in turn for documents of 1-16, 17-32 and 33-64 words,
+    matches the oracle under the resident schedule, runs the same arithmetic
+    under the per-iteration schedule (bitwise: w and u go through memory in the
+    permuted order and come back) and agrees under the unfused one."""
+    rng = np.random.default_rng(60 + vr)
+    lengths = np.concatenate([rng.integers(1, 17, size=24), rng.integers(17, 33, size=24),
+                              rng.integers(33, 65, size=24)])
+    c = handmade_corpus(rng, 3000, 40, lengths)
+    ids = rng.choice(3000, size=vr, replace=False).astype(np.int32)
+    q = synth.Queries(q_ptr=np.array([0, vr]), ids=ids, weights=rng.integers(1, 4, size=vr).astype(np.float32))
+    ref = oracle_support(c, ids, q.weights, 10.0, 15)
+    corpus = corpus_of(W, c)
+    S = (vr + 3) // 4 * 4
+    tested = 0
+    for cap in (16, 32, 64):
+        for sh in corpus.sink_candidates(S, cap):
+            if sh["maxw"] != 1 or sh["stream"] or sh["lg_cg"] not in (1, 2):
+                continue
+            try:
+                corpus.set_sink_shape(S, cap, sh)
+            except W.WMDError:
+                continue  # a shape the library cannot run for this bucket
+            what = f"S={S} cap={cap} shape={sh}"
+            res = run(W, corpus, q, 10.0, 15)[0]
+            per = run(W, corpus, q, 10.0, 15, schedule="per_iteration")[0]
+            unf = run(W, corpus, q, 10.0, 15, schedule="unfused")[0]
+            assert_close(res, ref, TOL32, what)
+            assert np.array_equal(per, res), what
+            assert_close(unf, res, 1e-6, what)
+            tested += 1
+        corpus.set_sink_shape(S, cap, None)
+    assert tested >= 3, f"only {tested} permuted-slot shapes ran for S={S}"
