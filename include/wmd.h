@@ -136,14 +136,20 @@ typedef struct {
   const int32_t* q_ids;       /* device, q_ptr[B] word ids                             */
   const float* q_weights;     /* device, q_ptr[B] weights                              */
   float lambda;               /* entropic weight, finite, > 0: K = exp(-lambda M).
-                                 Range: K is float32 and is not rescaled (the paper's
-                                 iteration has no log-domain form).  While every
-                                 document word has some query word with lambda M below
-                                 about 87 (exp above the smallest normal float) the
-                                 results keep float32 accuracy; a document with a word
-                                 whose whole row of K underflows scores +Inf (below).
-                                 With N(0, 1/d) embeddings, where distinct words lie
-                                 about 1.0-1.5 apart, that holds up to lambda ~ 60.     */
+                                 Range: K is float32.  Each row of K (one vocabulary
+                                 word against the query's words) is stored scaled by
+                                 exp(lambda m_j), m_j the row's smallest cost: exact for
+                                 the iteration (the document-side scaling absorbs the
+                                 factor) and taken out again in the final pass, so no
+                                 row underflows.  A query word
+                                 whose lambda (M_ij - m_j) exceeds about 87 (exp below
+                                 the smallest normal float) for every word of a
+                                 document still breaks the float32 iteration there:
+                                 that document scores +Inf (below).  With N(0, 1/d)
+                                 embeddings at d = 300, results keep float32 accuracy
+                                 for lambda from 1 to 300 (tested); in few dimensions
+                                 distances spread further and the limit comes sooner
+                                 (d = 8: some documents flagged at lambda 50).         */
   int32_t max_iter;           /* Sinkhorn-Knopp iterations, 0..100000                  */
   int32_t cdist;              /* wmd_cdist                                             */
   int32_t schedule;           /* wmd_schedule                                          */
