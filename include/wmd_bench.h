@@ -1,7 +1,7 @@
 /*
  * wmd_bench.h -- measurement kernels of libwmd.so.
  *
- * Not part of the method: they measure the ceilings the hot path is judged
+ * Not part of the method: they measure the ceilings the hot path is measured
  * against.  The paper models its fused SDDMM-SpMM as bound by memory bandwidth
  * (Section III-E) and quotes the machine's bandwidths in Table II; on a GPU
  * the Sinkhorn kernels' bytes come from two places -- a stream of the corpus

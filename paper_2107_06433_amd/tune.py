@@ -69,7 +69,7 @@ def tune_workload(name: str, cdist: str = "fp32", reps: int = 2, max_candidates:
     R = max(len(v) for v in cands.values())
     log(f"[tune] {name}: {len(pairs)} (S, cap) pairs, up to {R} candidates each, {Q.B} queries")
     # Shapes are timed in the regime the workload runs in: the whole batch in
-    # one call (launch groups overlap on the side streams, so a shape is judged
+    # one call (launch groups overlap on the side streams, so a shape is ranked
     # by its time while sharing the device), or with per_query one query per
     # call (each launch alone on the device, which favours latency).
     if per_query:
